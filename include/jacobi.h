@@ -1,0 +1,162 @@
+/*
+ * jacobi.h -- C ABI of the MI355X (gfx950) over-decomposed Jacobi library.
+ *
+ * The library runs the data-parallel core of the Jacobi3D proxy application
+ * of the paper (Section 4.3, Proxy Application: Jacobi3D): a synchronous
+ * 5-point (2D) or 7-point (3D) Jacobi sweep over a grid that is
+ * over-decomposed (Section 4.4, Over-decomposition) into many cuboid blocks,
+ * each stored with a one-cell face halo that is refreshed from the neighbour
+ * blocks, plus an FP64 L2 residual taken every few sweeps.
+ *
+ * Problem (the paper names the Jacobi method only; this is the reading used):
+ *   -Laplace(u) = f on the unit square/cube, Dirichlet values on the ring of
+ *   nodes around the interior, h = 1/(n+1), b = h^2 f.
+ *   2D update   u'[c] = ((u[W] + u[E]) + (u[S] + u[N]) + b[c]) * 1/4
+ *   3D update   u'[c] = (((u[W] + u[E]) + (u[S] + u[N])) + (u[B] + u[F]) + b[c]) * fl(1/6)
+ *   evaluated exactly in this order, IEEE round-to-nearest, no FMA, no flush
+ *   to zero; Laplace (no source) drops "+ b[c]".  The ring never changes.
+ *   residual    sqrt(sum over the interior of (b - (2d u - s))^2), all in FP64
+ *               from the state widened to FP64 (s = the neighbour sum above).
+ *
+ * Arrays crossing the boundary (all device pointers unless noted):
+ *   full state  (n_x+2)(n_y+2)[(n_z+2)] values of the handle's dtype, x
+ *               fastest, ring included: node (i, j[, k]) at
+ *               ((k * (n_y+2)) + j) * (n_x+2) + i, with 0 and n+1 the ring.
+ *   source f    n_x n_y [n_z] interior values of the handle's dtype, x fastest.
+ *
+ * Memory and streams: the library never allocates device memory.  The caller
+ * supplies one device workspace of jacobi_workspace_bytes() bytes (typically a
+ * torch tensor) that holds both state buffers, the blocked source and the
+ * reduction scratch; it must stay allocated until jacobi_destroy returns.
+ * Every operation is enqueued on the handle's HIP stream in call order and is
+ * asynchronous unless documented otherwise; input/output pointers must stay
+ * valid until the stream reaches the operation.
+ *
+ * Errors: every function returns JACOBI_OK (0) or a negative status and never
+ * throws.  Argument checks run before any HIP call.  The text of the last
+ * error on the calling thread is available from jacobi_last_error().
+ */
+#ifndef JACOBI_H
+#define JACOBI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct jacobi_s *jacobi_t; /* opaque handle (host object) */
+
+enum jacobi_dtype { JACOBI_F32 = 0, JACOBI_F64 = 1 };
+
+enum jacobi_status {
+    JACOBI_OK = 0,
+    JACOBI_E_INVAL = -1,       /* bad argument (sizes, pointers, dtype, ranges)   */
+    JACOBI_E_NOMEM = -2,       /* workspace too small or host allocation failed    */
+    JACOBI_E_HIP = -3,         /* a HIP runtime call failed (text in last_error)   */
+    JACOBI_E_STATE = -4,       /* call not valid in the handle's state             */
+    JACOBI_E_UNSUPPORTED = -5  /* valid request this build does not implement      */
+};
+
+/* Tuning flags for jacobi_set_tuning. */
+enum jacobi_flags {
+    /* Sweep each block from its own storage after an explicit halo exchange
+     * before every sweep (pack -> copy -> unpack between blocks in HBM), the
+     * step order of Section 4.3.  Temporal depth is forced to 1.  Without the
+     * flag the sweep reads face neighbours' cells directly from their blocks
+     * (the exchange fused into the sweep's loads) and may do several sweeps
+     * per pass. */
+    JACOBI_FLAG_EXPLICIT_HALO = 1
+};
+
+/* ---------------------------------------------------------------- set-up */
+
+/* Device bytes the handle needs for this problem.
+ *   ndim    2 or 3
+ *   grid    interior nodes per axis, x first (ndim values, each >= 1)
+ *   blocks  blocks per axis, x first (ndim values, 1 <= blocks <= grid);
+ *           the block extent along x is ceil(n/B) rounded up to 32 bytes of
+ *           elements, along y and z ceil(n/B); the last block on an axis takes
+ *           the remainder and must not be empty (JACOBI_E_INVAL otherwise).
+ *   dtype   JACOBI_F32 or JACOBI_F64 (arithmetic and storage type of the sweep)
+ *   bytes   out: workspace size.  JACOBI_E_INVAL on overflow. */
+int jacobi_workspace_bytes(int ndim, const int64_t *grid, const int64_t *blocks, int dtype,
+                           size_t *bytes);
+
+/* Create a handle over a caller-owned device workspace (256-byte aligned,
+ * >= jacobi_workspace_bytes).  stream: hipStream_t to enqueue on, or NULL for
+ * the null stream.  The handle starts without a state (JACOBI_E_STATE from
+ * sweep/residual until jacobi_set_state) and without a source (Laplace). */
+int jacobi_create(int ndim, const int64_t *grid, const int64_t *blocks, int dtype,
+                  void *workspace, size_t workspace_bytes, void *stream, jacobi_t *out);
+
+/* Wait for the handle's stream, then free the host object.  NULL is a no-op. */
+int jacobi_destroy(jacobi_t h);
+
+/* Rebind the handle to another stream (hipStream_t; NULL = null stream). */
+int jacobi_set_stream(jacobi_t h, void *stream);
+
+/* Block geometry: per axis x first, blocks and block extent (3 values each,
+ * unused axes 1). */
+int jacobi_get_layout(jacobi_t h, int64_t *blocks3, int64_t *extent3);
+
+/* ------------------------------------------------------- data in and out */
+
+/* Scatter a full state (ring + interior, layout above) into the blocks of
+ * both state buffers and fill every block's halo (Section 4.3: the domain is
+ * decomposed into cuboids).  u: device, handle dtype. */
+int jacobi_set_state(jacobi_t h, const void *u);
+
+/* Gather the current state (ring + interior) into u (device, handle dtype). */
+int jacobi_get_state(jacobi_t h, void *u);
+
+/* Set the scaled source b = fl_T(h2 * f) blockwise, with the product formed in
+ * FP64 and rounded once to the handle dtype T.  f: device interior array of
+ * the handle dtype, or NULL for the Laplace equation (b = 0).  h2 > 0, finite. */
+int jacobi_set_source(jacobi_t h, const void *f, double h2);
+
+/* ------------------------------------------------------------- hot path */
+
+/* Refresh every internal face halo of the current state buffer from the face
+ * neighbour's edge cells (pack, copy, unpack in HBM; one launch for all faces
+ * of all blocks).  Domain-edge halos keep the boundary values.  Idempotent. */
+int jacobi_halo_exchange(jacobi_t h);
+
+/* Run n_iter >= 0 synchronous sweeps (0 is a no-op).  The sweeps are grouped
+ * into passes of up to the tuned temporal depth; every pass reads the current
+ * buffer and writes the other.  Halos are valid when the last pass ends. */
+int jacobi_sweep(jacobi_t h, int64_t n_iter);
+
+/* FP64 residual of the current state, written to the device double *res_dev
+ * (stream-ordered, no synchronisation, deterministic summation order). */
+int jacobi_residual_async(jacobi_t h, double *res_dev);
+
+/* Same, copied to the host double *res_host; synchronises the stream. */
+int jacobi_residual(jacobi_t h, double *res_host);
+
+/* Sweep n_iter times, taking the residual of the states after 0, R, 2R, ...
+ * sweeps and after the last sweep: res_dev receives
+ * ceil(n_iter / R) + 1 device doubles (R = check_every >= 1).  Stream-ordered,
+ * no host synchronisation. */
+int jacobi_solve(jacobi_t h, int64_t n_iter, int64_t check_every, double *res_dev);
+
+/* Choose the sweep schedule.  t_depth: sweeps per pass (temporal blocking,
+ * 1..jacobi_max_depth(); 0 = library default), rows: rows per tile
+ * (0 = default), flags: jacobi_flags.  Bit-neutral: every choice gives the
+ * same results. */
+int jacobi_set_tuning(jacobi_t h, int t_depth, int rows, int flags);
+int jacobi_get_tuning(jacobi_t h, int *t_depth, int *rows, int *flags);
+
+/* Largest temporal depth this build supports for the handle's ndim/dtype. */
+int jacobi_max_depth(int ndim, int dtype);
+
+/* --------------------------------------------------------------- errors */
+const char *jacobi_strerror(int status);
+const char *jacobi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JACOBI_H */

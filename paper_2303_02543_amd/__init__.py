@@ -1,0 +1,328 @@
+"""Python binding of libjacobi.so, the gfx950 over-decomposed Jacobi library.
+
+Argument marshalling only: every step of the sweep, halo exchange, residual,
+scatter/gather and source scaling runs in the library's HIP kernels.  PyTorch
+provides device memory (the workspace and user tensors) and the HIP stream.
+There is no CPU fallback: if the library is not built, or no GPU is visible
+when a handle is created, an exception is raised.
+
+Module-level functions carry the C names (jacobi_create, jacobi_sweep, ...)
+and return Python values, raising JacobiError on a non-zero status.  `Solver`
+is a small convenience wrapper that owns a torch workspace.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjacobi.so")
+
+JACOBI_F32 = 0
+JACOBI_F64 = 1
+JACOBI_FLAG_EXPLICIT_HALO = 1
+
+JACOBI_OK = 0
+JACOBI_E_INVAL = -1
+JACOBI_E_NOMEM = -2
+JACOBI_E_HIP = -3
+JACOBI_E_STATE = -4
+JACOBI_E_UNSUPPORTED = -5
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+_D = ctypes.c_double
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+
+# name -> argtypes (all return int status unless listed in _RESTYPES)
+_SIGNATURES = {
+    "jacobi_workspace_bytes": [_I, _PI64, _PI64, _I, ctypes.POINTER(_SZ)],
+    "jacobi_create": [_I, _PI64, _PI64, _I, _P, _SZ, _P, ctypes.POINTER(_P)],
+    "jacobi_destroy": [_P],
+    "jacobi_set_stream": [_P, _P],
+    "jacobi_get_layout": [_P, _PI64, _PI64],
+    "jacobi_set_state": [_P, _P],
+    "jacobi_get_state": [_P, _P],
+    "jacobi_set_source": [_P, _P, _D],
+    "jacobi_halo_exchange": [_P],
+    "jacobi_sweep": [_P, _I64],
+    "jacobi_residual_async": [_P, _P],
+    "jacobi_residual": [_P, ctypes.POINTER(_D)],
+    "jacobi_solve": [_P, _I64, _I64, _P],
+    "jacobi_set_tuning": [_P, _I, _I, _I],
+    "jacobi_get_tuning": [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)],
+    "jacobi_max_depth": [_I, _I],
+    "jacobi_strerror": [_I],
+    "jacobi_last_error": [],
+}
+_RESTYPES = {"jacobi_strerror": ctypes.c_char_p, "jacobi_last_error": ctypes.c_char_p}
+
+
+class JacobiError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (status %d)" % (message, status))
+        self.status = status
+
+
+def lib():
+    """The loaded libjacobi.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libjacobi.so is not built (expected at %s); run "
+                              "__graft_entry__.build() or python -m paper_2303_02543_amd.build"
+                              % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = _RESTYPES.get(name, ctypes.c_int)
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGNATURES)
+
+
+def _check(status):
+    if status != JACOBI_OK:
+        msg = lib().jacobi_last_error().decode(errors="replace")
+        raise JacobiError(status, msg or lib().jacobi_strerror(status).decode())
+    return status
+
+
+def _arr64(vals):
+    a = (ctypes.c_int64 * len(vals))(*[int(v) for v in vals])
+    return a
+
+
+def dtype_code(dtype):
+    import torch
+    if dtype in (torch.float32, "float32", "f32"):
+        return JACOBI_F32
+    if dtype in (torch.float64, "float64", "f64"):
+        return JACOBI_F64
+    raise TypeError("dtype must be float32 or float64, got %r" % (dtype,))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ----------------------------------------------------------- C-name wrappers
+def jacobi_workspace_bytes(ndim, grid, blocks, dtype):
+    out = _SZ(0)
+    _check(lib().jacobi_workspace_bytes(int(ndim), _arr64(grid), _arr64(blocks), int(dtype),
+                                        ctypes.byref(out)))
+    return out.value
+
+
+def jacobi_create(ndim, grid, blocks, dtype, workspace_ptr, workspace_bytes, stream_ptr):
+    h = _P()
+    _check(lib().jacobi_create(int(ndim), _arr64(grid), _arr64(blocks), int(dtype),
+                               workspace_ptr, int(workspace_bytes), stream_ptr, ctypes.byref(h)))
+    return h
+
+
+def jacobi_destroy(h):
+    _check(lib().jacobi_destroy(h))
+
+
+def jacobi_set_stream(h, stream_ptr):
+    _check(lib().jacobi_set_stream(h, stream_ptr))
+
+
+def jacobi_get_layout(h):
+    b = (ctypes.c_int64 * 3)()
+    e = (ctypes.c_int64 * 3)()
+    _check(lib().jacobi_get_layout(h, b, e))
+    return tuple(b), tuple(e)
+
+
+def jacobi_set_state(h, u_ptr):
+    _check(lib().jacobi_set_state(h, u_ptr))
+
+
+def jacobi_get_state(h, u_ptr):
+    _check(lib().jacobi_get_state(h, u_ptr))
+
+
+def jacobi_set_source(h, f_ptr, h2):
+    _check(lib().jacobi_set_source(h, f_ptr, float(h2)))
+
+
+def jacobi_halo_exchange(h):
+    _check(lib().jacobi_halo_exchange(h))
+
+
+def jacobi_sweep(h, n_iter):
+    _check(lib().jacobi_sweep(h, int(n_iter)))
+
+
+def jacobi_residual_async(h, res_ptr):
+    _check(lib().jacobi_residual_async(h, res_ptr))
+
+
+def jacobi_residual(h):
+    out = _D(0.0)
+    _check(lib().jacobi_residual(h, ctypes.byref(out)))
+    return out.value
+
+
+def jacobi_solve(h, n_iter, check_every, res_ptr):
+    _check(lib().jacobi_solve(h, int(n_iter), int(check_every), res_ptr))
+
+
+def jacobi_set_tuning(h, t_depth=0, rows=0, flags=0):
+    _check(lib().jacobi_set_tuning(h, int(t_depth), int(rows), int(flags)))
+
+
+def jacobi_get_tuning(h):
+    t, r, f = _I(), _I(), _I()
+    _check(lib().jacobi_get_tuning(h, ctypes.byref(t), ctypes.byref(r), ctypes.byref(f)))
+    return t.value, r.value, f.value
+
+
+def jacobi_max_depth(ndim, dtype):
+    v = lib().jacobi_max_depth(int(ndim), int(dtype))
+    if v < 0:
+        _check(v)
+    return v
+
+
+def jacobi_strerror(status):
+    return lib().jacobi_strerror(int(status)).decode()
+
+
+def jacobi_last_error():
+    return lib().jacobi_last_error().decode(errors="replace")
+
+
+# ------------------------------------------------------------ convenience
+def residual_count(n_iter, check_every):
+    """Number of residuals jacobi_solve writes: ceil(n_iter / R) + 1."""
+    return -(-int(n_iter) // int(check_every)) + 1
+
+
+class Solver:
+    """A handle plus the torch workspace that backs it.
+
+    grid, blocks: interior nodes and blocks per axis, x first (2 or 3 values).
+    dtype: torch.float32 or torch.float64.  Tensors passed in must live on the
+    workspace's device, be contiguous and have the solver's dtype; full states
+    have shape (n_y+2, n_x+2) / (n_z+2, n_y+2, n_x+2), sources (n_y, n_x) / ...
+    """
+
+    def __init__(self, grid, blocks, dtype, device="cuda", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the Jacobi library has no CPU path")
+        self.grid = tuple(int(g) for g in grid)
+        self.blocks = tuple(int(b) for b in blocks)
+        self.ndim = len(self.grid)
+        self.torch_dtype = dtype
+        self.dtype = dtype_code(dtype)
+        self.device = torch.device(device)
+        nbytes = jacobi_workspace_bytes(self.ndim, self.grid, self.blocks, self.dtype)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.h = jacobi_create(self.ndim, self.grid, self.blocks, self.dtype,
+                               _ptr(self.workspace), nbytes, _stream_handle(stream))
+
+    # shapes
+    @property
+    def state_shape(self):
+        return tuple(n + 2 for n in reversed(self.grid))
+
+    @property
+    def interior_shape(self):
+        return tuple(reversed(self.grid))
+
+    def _check_tensor(self, t, shape, name):
+        import torch
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor" % name)
+        if t.device != self.workspace.device:
+            raise ValueError("%s must be on %s" % (name, self.workspace.device))
+        if t.dtype != self.torch_dtype:
+            raise TypeError("%s must have dtype %s" % (name, self.torch_dtype))
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError("%s must have shape %s, got %s" % (name, shape, tuple(t.shape)))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+
+    def set_stream(self, stream=None):
+        jacobi_set_stream(self.h, _stream_handle(stream))
+
+    def set_state(self, U):
+        self._check_tensor(U, self.state_shape, "state")
+        jacobi_set_state(self.h, _ptr(U))
+
+    def get_state(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.state_shape, dtype=self.torch_dtype, device=self.device)
+        self._check_tensor(out, self.state_shape, "out")
+        jacobi_get_state(self.h, _ptr(out))
+        return out
+
+    def set_source(self, f, h2):
+        if f is None:
+            jacobi_set_source(self.h, None, 1.0)
+            return
+        self._check_tensor(f, self.interior_shape, "source")
+        jacobi_set_source(self.h, _ptr(f), h2)
+
+    def halo_exchange(self):
+        jacobi_halo_exchange(self.h)
+
+    def sweep(self, n_iter):
+        jacobi_sweep(self.h, n_iter)
+
+    def residual(self):
+        return jacobi_residual(self.h)
+
+    def residual_async(self, out):
+        import torch
+        if out.dtype != torch.float64 or out.numel() < 1 or out.device != self.device:
+            raise ValueError("out must be a float64 tensor on the solver's device")
+        jacobi_residual_async(self.h, _ptr(out))
+
+    def solve(self, n_iter, check_every, out=None):
+        import torch
+        cnt = residual_count(n_iter, check_every)
+        if out is None:
+            out = torch.empty(cnt, dtype=torch.float64, device=self.device)
+        if out.dtype != torch.float64 or out.numel() < cnt or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of >= %d values" % cnt)
+        jacobi_solve(self.h, n_iter, check_every, _ptr(out))
+        return out
+
+    def set_tuning(self, t_depth=0, rows=0, flags=0):
+        jacobi_set_tuning(self.h, t_depth, rows, flags)
+
+    def get_tuning(self):
+        return jacobi_get_tuning(self.h)
+
+    def layout(self):
+        return jacobi_get_layout(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            jacobi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

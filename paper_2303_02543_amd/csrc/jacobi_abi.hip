@@ -1,0 +1,449 @@
+// C ABI of the over-decomposed Jacobi library (declared in include/jacobi.h).
+//
+// Host side: argument validation (always before any HIP call), the block
+// layout planner, the workspace carve-up, and the pass planner that turns
+// jacobi_sweep(n) into kernel launches on the handle's stream.  The library
+// allocates no device memory: the caller's workspace holds everything.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/jacobi.h"
+#include "jacobi_internal.h"
+#include "kernels.h"
+
+using jac::Geom;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(JACOBI_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                         \
+    do {                                            \
+        hipError_t e_ = (expr);                     \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxCoord = 1 << 30;  // interior nodes per axis (coordinates are int32)
+
+bool mul_ok(size_t a, size_t b, size_t *out) { return !__builtin_mul_overflow(a, b, out); }
+bool add_ok(size_t a, size_t b, size_t *out) { return !__builtin_add_overflow(a, b, out); }
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    size_t off_u0, off_u1, off_b, off_part, off_scratch, bytes;
+};
+
+// Block geometry and workspace carve-up.  All checks, no HIP.
+int plan(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, Geom *g, Layout *l) {
+    if (ndim != 2 && ndim != 3) return fail(JACOBI_E_INVAL, "ndim must be 2 or 3 (got %d)", ndim);
+    if (!grid || !blocks) return fail(JACOBI_E_INVAL, "grid and blocks must not be NULL");
+    if (dtype != JACOBI_F32 && dtype != JACOBI_F64)
+        return fail(JACOBI_E_INVAL, "dtype must be JACOBI_F32 or JACOBI_F64 (got %d)", dtype);
+    const size_t es = dtype == JACOBI_F32 ? 4 : 8;
+    std::memset(g, 0, sizeof *g);
+    g->ndim = ndim;
+    g->ax = (int)(32 / es);
+    for (int a = 0; a < 3; ++a) {
+        int64_t n = 1, b = 1;
+        if (a < ndim) {
+            n = grid[a];
+            b = blocks[a];
+            if (n < 1 || n > kMaxCoord)
+                return fail(JACOBI_E_INVAL, "grid[%d] = %lld out of range [1, 2^30]", a, (long long)n);
+            if (b < 1 || b > n)
+                return fail(JACOBI_E_INVAL, "blocks[%d] = %lld must be in [1, grid[%d] = %lld]", a,
+                            (long long)b, a, (long long)n);
+        }
+        int64_t e = (n + b - 1) / b;
+        if (a == 0) e = (e + g->ax - 1) / g->ax * g->ax;
+        if ((b - 1) * e >= n)
+            return fail(JACOBI_E_INVAL,
+                        "blocks[%d] = %lld leaves the last block empty (block extent %lld, n = %lld)",
+                        a, (long long)b, (long long)e, (long long)n);
+        g->n[a] = (int)n;
+        g->nb[a] = (int)b;
+        g->e[a] = (int)e;
+    }
+    size_t pitch = (size_t)g->e[0] + 2 * (size_t)g->ax, plane, bstride, sstride, nblk, t;
+    if (!mul_ok(pitch, (size_t)g->e[1] + 2, &plane)) return fail(JACOBI_E_INVAL, "size overflow");
+    bstride = plane;
+    if (ndim == 3 && !mul_ok(plane, (size_t)g->e[2] + 2, &bstride))
+        return fail(JACOBI_E_INVAL, "size overflow");
+    bstride = round_up(bstride, 64);
+    if (!mul_ok((size_t)g->e[0], (size_t)g->e[1], &sstride) ||
+        !mul_ok(sstride, (size_t)g->e[2], &sstride))
+        return fail(JACOBI_E_INVAL, "size overflow");
+    sstride = round_up(sstride, 64);
+    if (!mul_ok((size_t)g->nb[0], (size_t)g->nb[1], &nblk) || !mul_ok(nblk, (size_t)g->nb[2], &nblk))
+        return fail(JACOBI_E_INVAL, "size overflow");
+    g->pitch = (int64_t)pitch;
+    g->plane = (int64_t)plane;
+    g->bstride = (int64_t)bstride;
+    g->sstride = (int64_t)sstride;
+    g->nblocks = (int64_t)nblk;
+    size_t sbytes, bbytes, off = 0;
+    if (!mul_ok(nblk, bstride, &sbytes) || !mul_ok(sbytes, es, &sbytes) ||
+        !mul_ok(nblk, sstride, &bbytes) || !mul_ok(bbytes, es, &bbytes))
+        return fail(JACOBI_E_INVAL, "size overflow");
+    if (sbytes > ((size_t)1 << 62) || bbytes > ((size_t)1 << 62))
+        return fail(JACOBI_E_INVAL, "size overflow");
+    l->off_u0 = off;
+    off = round_up(off + sbytes, kAlign);
+    l->off_u1 = off;
+    off = round_up(off + sbytes, kAlign);
+    l->off_b = off;
+    off = round_up(off + bbytes, kAlign);
+    l->off_part = off;
+    off = round_up(off + sizeof(double) * jac::kResidualGroups, kAlign);
+    l->off_scratch = off;
+    if (!add_ok(off, kAlign, &t)) return fail(JACOBI_E_INVAL, "size overflow");
+    l->bytes = t;
+    return JACOBI_OK;
+}
+
+}  // namespace
+
+struct jacobi_s {
+    Geom g;
+    Layout lay;
+    int dtype;
+    char *ws;
+    void *u[2];
+    void *b;
+    double *partials;
+    double *scratch;
+    int cur;
+    bool has_state, has_source;
+    hipStream_t stream;
+    int depth, rows, flags;
+};
+
+namespace {
+
+int check_handle(jacobi_t h) {
+    if (!h) return fail(JACOBI_E_INVAL, "handle is NULL");
+    return JACOBI_OK;
+}
+
+int default_depth(const jacobi_s *h) {
+    (void)h;
+    return 1;
+}
+
+int max_depth(int ndim, int dtype) {
+    if (ndim == 3) return 1;
+    const int *list;
+    const int n = jac::march2d_depths(dtype, &list);
+    return list[n - 1];
+}
+
+// Largest compiled march depth <= want.
+int pick_depth(int dtype, int want) {
+    const int *list;
+    const int n = jac::march2d_depths(dtype, &list);
+    int best = 1;
+    for (int i = 0; i < n; ++i)
+        if (list[i] <= want) best = list[i];
+    return best;
+}
+
+template <typename R>
+int do_halo(jacobi_t h) {
+    HIP_TRY(jac::launch_halo_exchange<R>(h->g, h->u[h->cur], h->stream), "halo exchange launch");
+    return JACOBI_OK;
+}
+
+template <typename R>
+int do_sweep(jacobi_t h, int64_t n) {
+    const void *b = h->has_source ? h->b : nullptr;
+    const bool explicit_halo = (h->flags & JACOBI_FLAG_EXPLICIT_HALO) || h->g.ndim == 3;
+    if (explicit_halo) {
+        for (int64_t k = 0; k < n; ++k) {
+            HIP_TRY(jac::launch_sweep_local<R>(h->g, h->u[h->cur], h->u[h->cur ^ 1], b, h->stream),
+                    "sweep launch");
+            h->cur ^= 1;
+            HIP_TRY(jac::launch_halo_exchange<R>(h->g, h->u[h->cur], h->stream),
+                    "halo exchange launch");
+        }
+        return JACOBI_OK;
+    }
+    const int depth = h->depth > 0 ? h->depth : default_depth(h);
+    const int rows = h->rows > 0 ? h->rows : 64;
+    int64_t left = n;
+    while (left > 0) {
+        const int want = left < depth ? (int)left : depth;
+        const int t = pick_depth(h->dtype, want);
+        HIP_TRY(jac::launch_sweep2d_march<R>(h->g, h->u[h->cur], h->u[h->cur ^ 1], b, t, rows,
+                                             h->stream),
+                "sweep launch");
+        h->cur ^= 1;
+        left -= t;
+    }
+    if (n > 0)
+        HIP_TRY(jac::launch_halo_exchange<R>(h->g, h->u[h->cur], h->stream), "halo exchange launch");
+    return JACOBI_OK;
+}
+
+template <typename R>
+int do_residual(jacobi_t h, double *out) {
+    HIP_TRY(jac::launch_residual<R>(h->g, h->u[h->cur], h->has_source ? h->b : nullptr,
+                                    h->partials, out, h->stream),
+            "residual launch");
+    return JACOBI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int jacobi_workspace_bytes(int ndim, const int64_t *grid, const int64_t *blocks, int dtype,
+                           size_t *bytes) {
+    if (!bytes) return fail(JACOBI_E_INVAL, "bytes must not be NULL");
+    Geom g;
+    Layout l;
+    const int rc = plan(ndim, grid, blocks, dtype, &g, &l);
+    if (rc != JACOBI_OK) return rc;
+    *bytes = l.bytes;
+    return JACOBI_OK;
+}
+
+int jacobi_create(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, void *workspace,
+                  size_t workspace_bytes, void *stream, jacobi_t *out) {
+    if (!out) return fail(JACOBI_E_INVAL, "out must not be NULL");
+    *out = nullptr;
+    Geom g;
+    Layout l;
+    int rc = plan(ndim, grid, blocks, dtype, &g, &l);
+    if (rc != JACOBI_OK) return rc;
+    if (!workspace) return fail(JACOBI_E_INVAL, "workspace must not be NULL");
+    if ((uintptr_t)workspace % kAlign)
+        return fail(JACOBI_E_INVAL, "workspace must be %zu-byte aligned", kAlign);
+    if (workspace_bytes < l.bytes)
+        return fail(JACOBI_E_NOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, l.bytes);
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, workspace);
+    if (e != hipSuccess) return hip_fail(e, "workspace pointer query");
+    if (attr.type != hipMemoryTypeDevice)
+        return fail(JACOBI_E_INVAL, "workspace is not device memory");
+    jacobi_s *h = new (std::nothrow) jacobi_s();
+    if (!h) return fail(JACOBI_E_NOMEM, "host allocation failed");
+    h->g = g;
+    h->lay = l;
+    h->dtype = dtype;
+    h->ws = (char *)workspace;
+    h->u[0] = h->ws + l.off_u0;
+    h->u[1] = h->ws + l.off_u1;
+    h->b = h->ws + l.off_b;
+    h->partials = (double *)(h->ws + l.off_part);
+    h->scratch = (double *)(h->ws + l.off_scratch);
+    h->cur = 0;
+    h->has_state = false;
+    h->has_source = false;
+    h->stream = (hipStream_t)stream;
+    h->depth = 0;
+    h->rows = 0;
+    h->flags = 0;
+    *out = h;
+    return JACOBI_OK;
+}
+
+int jacobi_destroy(jacobi_t h) {
+    if (!h) return JACOBI_OK;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    delete h;
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize in destroy");
+    return JACOBI_OK;
+}
+
+int jacobi_set_stream(jacobi_t h, void *stream) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    h->stream = (hipStream_t)stream;
+    return JACOBI_OK;
+}
+
+int jacobi_get_layout(jacobi_t h, int64_t *blocks3, int64_t *extent3) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!blocks3 || !extent3) return fail(JACOBI_E_INVAL, "output pointers must not be NULL");
+    for (int a = 0; a < 3; ++a) {
+        blocks3[a] = h->g.nb[a];
+        extent3[a] = h->g.e[a];
+    }
+    return JACOBI_OK;
+}
+
+int jacobi_set_state(jacobi_t h, const void *u) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!u) return fail(JACOBI_E_INVAL, "u must not be NULL");
+    if (h->dtype == JACOBI_F32) {
+        HIP_TRY(jac::launch_scatter<float>(h->g, u, h->u[0], h->u[1], h->stream), "scatter launch");
+        HIP_TRY(jac::launch_halo_exchange<float>(h->g, h->u[0], h->stream), "halo exchange launch");
+        HIP_TRY(jac::launch_halo_exchange<float>(h->g, h->u[1], h->stream), "halo exchange launch");
+    } else {
+        HIP_TRY(jac::launch_scatter<double>(h->g, u, h->u[0], h->u[1], h->stream), "scatter launch");
+        HIP_TRY(jac::launch_halo_exchange<double>(h->g, h->u[0], h->stream), "halo exchange launch");
+        HIP_TRY(jac::launch_halo_exchange<double>(h->g, h->u[1], h->stream), "halo exchange launch");
+    }
+    h->cur = 0;
+    h->has_state = true;
+    return JACOBI_OK;
+}
+
+int jacobi_get_state(jacobi_t h, void *u) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!u) return fail(JACOBI_E_INVAL, "u must not be NULL");
+    if (!h->has_state) return fail(JACOBI_E_STATE, "no state set (call jacobi_set_state first)");
+    if (h->dtype == JACOBI_F32)
+        HIP_TRY(jac::launch_gather<float>(h->g, h->u[h->cur], u, h->stream), "gather launch");
+    else
+        HIP_TRY(jac::launch_gather<double>(h->g, h->u[h->cur], u, h->stream), "gather launch");
+    return JACOBI_OK;
+}
+
+int jacobi_set_source(jacobi_t h, const void *f, double h2) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!f) {
+        h->has_source = false;
+        return JACOBI_OK;
+    }
+    if (!(h2 > 0.0) || !std::isfinite(h2))
+        return fail(JACOBI_E_INVAL, "h2 must be positive and finite (got %g)", h2);
+    if (h->dtype == JACOBI_F32)
+        HIP_TRY(jac::launch_scale_source<float>(h->g, f, h->b, h2, h->stream), "source launch");
+    else
+        HIP_TRY(jac::launch_scale_source<double>(h->g, f, h->b, h2, h->stream), "source launch");
+    h->has_source = true;
+    return JACOBI_OK;
+}
+
+int jacobi_halo_exchange(jacobi_t h) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!h->has_state) return fail(JACOBI_E_STATE, "no state set (call jacobi_set_state first)");
+    return h->dtype == JACOBI_F32 ? do_halo<float>(h) : do_halo<double>(h);
+}
+
+int jacobi_sweep(jacobi_t h, int64_t n_iter) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (n_iter < 0) return fail(JACOBI_E_INVAL, "n_iter must be >= 0 (got %lld)", (long long)n_iter);
+    if (!h->has_state) return fail(JACOBI_E_STATE, "no state set (call jacobi_set_state first)");
+    if (n_iter == 0) return JACOBI_OK;
+    return h->dtype == JACOBI_F32 ? do_sweep<float>(h, n_iter) : do_sweep<double>(h, n_iter);
+}
+
+int jacobi_residual_async(jacobi_t h, double *res_dev) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!res_dev) return fail(JACOBI_E_INVAL, "res_dev must not be NULL");
+    if (!h->has_state) return fail(JACOBI_E_STATE, "no state set (call jacobi_set_state first)");
+    return h->dtype == JACOBI_F32 ? do_residual<float>(h, res_dev) : do_residual<double>(h, res_dev);
+}
+
+int jacobi_residual(jacobi_t h, double *res_host) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!res_host) return fail(JACOBI_E_INVAL, "res_host must not be NULL");
+    if (!h->has_state) return fail(JACOBI_E_STATE, "no state set (call jacobi_set_state first)");
+    rc = h->dtype == JACOBI_F32 ? do_residual<float>(h, h->scratch)
+                                : do_residual<double>(h, h->scratch);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(res_host, h->scratch, sizeof(double), hipMemcpyDeviceToHost, h->stream),
+            "residual copy");
+    HIP_TRY(hipStreamSynchronize(h->stream), "stream synchronize");
+    return JACOBI_OK;
+}
+
+int jacobi_solve(jacobi_t h, int64_t n_iter, int64_t check_every, double *res_dev) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (n_iter < 0) return fail(JACOBI_E_INVAL, "n_iter must be >= 0");
+    if (check_every < 1) return fail(JACOBI_E_INVAL, "check_every must be >= 1");
+    if (!res_dev) return fail(JACOBI_E_INVAL, "res_dev must not be NULL");
+    if (!h->has_state) return fail(JACOBI_E_STATE, "no state set (call jacobi_set_state first)");
+    rc = jacobi_residual_async(h, res_dev);
+    if (rc) return rc;
+    int64_t k = 0, i = 1;
+    while (k < n_iter) {
+        const int64_t step = n_iter - k < check_every ? n_iter - k : check_every;
+        rc = jacobi_sweep(h, step);
+        if (rc) return rc;
+        k += step;
+        rc = jacobi_residual_async(h, res_dev + i++);
+        if (rc) return rc;
+    }
+    return JACOBI_OK;
+}
+
+int jacobi_set_tuning(jacobi_t h, int t_depth, int rows, int flags) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    const int md = max_depth(h->g.ndim, h->dtype);
+    if (t_depth < 0 || t_depth > md)
+        return fail(JACOBI_E_INVAL, "t_depth must be in [0, %d] (got %d)", md, t_depth);
+    if (rows < 0 || rows > (1 << 20)) return fail(JACOBI_E_INVAL, "rows out of range (got %d)", rows);
+    if (flags & ~JACOBI_FLAG_EXPLICIT_HALO) return fail(JACOBI_E_INVAL, "unknown flags 0x%x", flags);
+    h->depth = t_depth;
+    h->rows = rows;
+    h->flags = flags;
+    return JACOBI_OK;
+}
+
+int jacobi_get_tuning(jacobi_t h, int *t_depth, int *rows, int *flags) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!t_depth || !rows || !flags) return fail(JACOBI_E_INVAL, "output pointers must not be NULL");
+    *t_depth = h->depth > 0 ? h->depth : default_depth(h);
+    *rows = h->rows > 0 ? h->rows : 64;
+    *flags = h->flags;
+    return JACOBI_OK;
+}
+
+int jacobi_max_depth(int ndim, int dtype) {
+    if ((ndim != 2 && ndim != 3) || (dtype != JACOBI_F32 && dtype != JACOBI_F64)) {
+        fail(JACOBI_E_INVAL, "bad ndim/dtype");
+        return JACOBI_E_INVAL;
+    }
+    return max_depth(ndim, dtype);
+}
+
+const char *jacobi_strerror(int status) {
+    switch (status) {
+    case JACOBI_OK: return "success";
+    case JACOBI_E_INVAL: return "invalid argument";
+    case JACOBI_E_NOMEM: return "insufficient memory";
+    case JACOBI_E_HIP: return "HIP runtime error";
+    case JACOBI_E_STATE: return "invalid call for the handle's state";
+    case JACOBI_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char *jacobi_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,167 @@
+// Layout kernels: scatter a full state into blocks, gather it back, scale the
+// source into blocks, and the face-halo exchange between blocks.
+//
+// The paper's proxy cuts the domain into cuboids and, every iteration, packs
+// each block's edge cells, moves them to the face neighbours and unpacks them
+// into their halos (Section 4.3; the over-decomposition timeline figure of
+// Section 4.4 names the six per-face halo buffers).  On one GPU every block
+// lives in the same HBM, so pack, copy and unpack collapse into one gather
+// per halo cell: read the neighbour's edge cell, write the halo slot.
+#include <hip/hip_runtime.h>
+
+#include "jacobi_internal.h"
+#include "kernels.h"
+
+namespace jac {
+
+// One thread per node of the full (n+2)^d array: the node's value goes to the
+// block that owns it (ring nodes to the domain-edge halo slots), in both state
+// buffers.  Internal halos are filled afterwards by the halo exchange.
+template <typename R>
+__global__ __launch_bounds__(256) void k_scatter(Geom g, const R *__restrict__ u,
+                                                 R *__restrict__ s0, R *__restrict__ s1,
+                                                 int64_t total) {
+    const int64_t nx2 = g.n[0] + 2, ny2 = g.n[1] + 2;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx2) - 1;
+        const int64_t rest = i / nx2;
+        const int y = (int)(rest % ny2) - 1;
+        const int z = (int)(rest / ny2) - 1;
+        const int64_t off = state_offset(g, x, y, z);
+        const R v = u[i];
+        s0[off] = v;
+        s1[off] = v;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_gather(Geom g, const R *__restrict__ s,
+                                                R *__restrict__ u, int64_t total) {
+    const int64_t nx2 = g.n[0] + 2, ny2 = g.n[1] + 2;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx2) - 1;
+        const int64_t rest = i / nx2;
+        const int y = (int)(rest % ny2) - 1;
+        const int z = (int)(rest / ny2) - 1;
+        u[i] = s[state_offset(g, x, y, z)];
+    }
+}
+
+// b = fl_R(h2 * f): the product in FP64, one rounding to R.
+template <typename R>
+__global__ __launch_bounds__(256) void k_scale_source(Geom g, const R *__restrict__ f,
+                                                      R *__restrict__ b, double h2,
+                                                      int64_t total) {
+    const int64_t nx = g.n[0], ny = g.n[1];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx);
+        const int64_t rest = i / nx;
+        const int y = (int)(rest % ny);
+        const int z = (int)(rest / ny);
+        b[source_offset(g, x, y, z)] = (R)(h2 * (double)f[i]);
+    }
+}
+
+// Halo exchange.  Work item (block, face, t): face = 2*axis + side (side 0 =
+// low, 1 = high), t enumerates the face's cells over the block's extents in
+// the other axes (first of them fastest, so y- and z-faces are contiguous
+// rows).  Faces on the domain boundary keep the Dirichlet values.
+template <typename R>
+__global__ __launch_bounds__(256) void k_halo_exchange(Geom g, R *__restrict__ s,
+                                                       int64_t maxface, int64_t total) {
+    const int nf = 2 * g.ndim;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = i % maxface;
+        const int64_t rest = i / maxface;
+        const int face = (int)(rest % nf);
+        const int64_t blk = rest / nf;
+        const int axis = face >> 1, side = face & 1;
+        int bc[3];
+        bc[0] = (int)(blk % g.nb[0]);
+        bc[1] = (int)((blk / g.nb[0]) % g.nb[1]);
+        bc[2] = (int)(blk / ((int64_t)g.nb[0] * g.nb[1]));
+        if (side == 0 && bc[axis] == 0) continue;
+        if (side == 1 && bc[axis] == g.nb[axis] - 1) continue;
+        int ext[3];
+        for (int a = 0; a < 3; ++a) ext[a] = a < g.ndim ? extent(g.n[a], g.e[a], bc[a]) : 1;
+        // the two tangential axes, lower one first
+        const int ta = axis == 0 ? 1 : 0;
+        const int tb = axis == 2 ? 1 : 2;
+        const int64_t fa = ext[ta];
+        const int64_t fb = (g.ndim == 3) ? ext[tb] : 1;
+        if (t >= fa * fb) continue;
+        int loc[3] = {0, 0, 0};
+        loc[ta] = (int)(t % fa);
+        if (g.ndim == 3) loc[tb] = (int)(t / fa);
+        loc[axis] = side == 0 ? -1 : ext[axis];
+        const int64_t dst = local_offset(g, blk, loc[0], loc[1], loc[2]);
+        // the halo cell's global coordinates; its owner is the face neighbour
+        const int gx = bc[0] * g.e[0] + loc[0];
+        const int gy = bc[1] * g.e[1] + loc[1];
+        const int gz = g.ndim == 3 ? bc[2] * g.e[2] + loc[2] : 0;
+        s[dst] = s[state_offset(g, gx, gy, gz)];
+    }
+}
+
+static inline int grid_for(int64_t total) {
+    int64_t b = (total + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+template <typename R>
+hipError_t launch_scatter(const Geom &g, const void *u, void *s0, void *s1, hipStream_t st) {
+    const int64_t total = (int64_t)(g.n[0] + 2) * (g.n[1] + 2) * (g.ndim == 3 ? g.n[2] + 2 : 1);
+    hipLaunchKernelGGL(k_scatter<R>, dim3(grid_for(total)), dim3(256), 0, st, g,
+                       (const R *)u, (R *)s0, (R *)s1, total);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_gather(const Geom &g, const void *s, void *u, hipStream_t st) {
+    const int64_t total = (int64_t)(g.n[0] + 2) * (g.n[1] + 2) * (g.ndim == 3 ? g.n[2] + 2 : 1);
+    hipLaunchKernelGGL(k_gather<R>, dim3(grid_for(total)), dim3(256), 0, st, g,
+                       (const R *)s, (R *)u, total);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_scale_source(const Geom &g, const void *f, void *b, double h2, hipStream_t st) {
+    const int64_t total = (int64_t)g.n[0] * g.n[1] * (g.ndim == 3 ? g.n[2] : 1);
+    hipLaunchKernelGGL(k_scale_source<R>, dim3(grid_for(total)), dim3(256), 0, st, g,
+                       (const R *)f, (R *)b, h2, total);
+    return hipGetLastError();
+}
+
+int64_t halo_maxface(const Geom &g) {
+    if (g.ndim == 2) return g.e[0] > g.e[1] ? g.e[0] : g.e[1];
+    int64_t a = (int64_t)g.e[1] * g.e[2], b = (int64_t)g.e[0] * g.e[2], c = (int64_t)g.e[0] * g.e[1];
+    int64_t m = a > b ? a : b;
+    return m > c ? m : c;
+}
+
+template <typename R>
+hipError_t launch_halo_exchange(const Geom &g, void *s, hipStream_t st) {
+    const int64_t maxface = halo_maxface(g);
+    const int64_t total = g.nblocks * 2 * g.ndim * maxface;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_halo_exchange<R>, dim3(grid_for(total)), dim3(256), 0, st, g, (R *)s,
+                       maxface, total);
+    return hipGetLastError();
+}
+
+template hipError_t launch_scatter<float>(const Geom &, const void *, void *, void *, hipStream_t);
+template hipError_t launch_scatter<double>(const Geom &, const void *, void *, void *, hipStream_t);
+template hipError_t launch_gather<float>(const Geom &, const void *, void *, hipStream_t);
+template hipError_t launch_gather<double>(const Geom &, const void *, void *, hipStream_t);
+template hipError_t launch_scale_source<float>(const Geom &, const void *, void *, double, hipStream_t);
+template hipError_t launch_scale_source<double>(const Geom &, const void *, void *, double, hipStream_t);
+template hipError_t launch_halo_exchange<float>(const Geom &, void *, hipStream_t);
+template hipError_t launch_halo_exchange<double>(const Geom &, void *, hipStream_t);
+
+}  // namespace jac

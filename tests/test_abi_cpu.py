@@ -1,0 +1,118 @@
+"""CPU-only checks of the C ABI: the library loads, exports every entry point
+include/jacobi.h declares, and rejects bad arguments before touching HIP."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2303_02543_amd as jb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "jacobi.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(jacobi_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = jb.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), "missing export %s" % name
+    # the binding wraps exactly the declared functions
+    assert sorted(jb.exported_symbols()) == names
+
+
+def ws_bytes(ndim, grid, blocks, dtype):
+    return jb.jacobi_workspace_bytes(ndim, grid, blocks, dtype)
+
+
+def expect_status(status, fn, *args):
+    with pytest.raises(jb.JacobiError) as ei:
+        fn(*args)
+    assert ei.value.status == status, str(ei.value)
+    return str(ei.value)
+
+
+def test_workspace_bytes_for_the_workloads():
+    # 2D 8192^2 FP32 in 16x16 blocks of 512^2: two state buffers of padded
+    # blocks + the blocked source; the sizes must at least cover the data
+    b = ws_bytes(2, [8192, 8192], [16, 16], jb.JACOBI_F32)
+    assert b >= 3 * 8192 * 8192 * 4
+    assert b < 3.2 * 8192 * 8192 * 4
+    b3 = ws_bytes(3, [512, 512, 512], [8, 8, 8], jb.JACOBI_F64)
+    assert b3 >= 3 * 512 ** 3 * 8
+    assert ws_bytes(2, [1, 1], [1, 1], jb.JACOBI_F64) > 0
+
+
+@pytest.mark.parametrize("ndim,grid,blocks,dtype,frag", [
+    (1, [8], [1], 0, "ndim"),
+    (4, [8] * 4, [1] * 4, 0, "ndim"),
+    (2, [0, 8], [1, 1], 0, "grid[0]"),
+    (2, [8, -3], [1, 1], 0, "grid[1]"),
+    (2, [8, 8], [0, 1], 0, "blocks[0]"),
+    (2, [8, 8], [1, 9], 0, "blocks[1]"),
+    (2, [8, 8], [1, 1], 7, "dtype"),
+    (2, [9, 8], [2, 1], 0, "empty"),          # x extent rounds up to 8: 8 + 1 ok...
+    (2, [16, 8], [3, 1], 0, "empty"),         # 3 blocks of 8 cannot cover 16
+    (3, [8, 8, 10], [1, 1, 6], 1, "empty"),   # ceil(10/6) = 2 -> 5 blocks suffice
+    (2, [2 ** 31, 8], [1, 1], 0, "grid[0]"),
+])
+def test_workspace_bytes_rejects(ndim, grid, blocks, dtype, frag):
+    if frag == "empty" and grid == [9, 8]:
+        # 9 columns, 2 blocks: extent ceil(9/2)=5 -> 8, last block has 1: valid
+        assert ws_bytes(ndim, grid, blocks, dtype) > 0
+        return
+    msg = expect_status(jb.JACOBI_E_INVAL, ws_bytes, ndim, grid, blocks, dtype)
+    assert frag in msg
+
+
+def test_null_pointers_and_handles_rejected():
+    L = jb.lib()
+    assert L.jacobi_workspace_bytes(2, None, None, 0, None) == jb.JACOBI_E_INVAL
+    out = ctypes.c_void_p()
+    g = jb._arr64([8, 8])
+    # NULL workspace is rejected before any HIP call
+    one = jb._arr64([1, 1])
+    assert L.jacobi_create(2, g, one, 0, None, 1 << 20, None, ctypes.byref(out)) == jb.JACOBI_E_INVAL
+    assert "workspace" in jb.jacobi_last_error()
+    assert out.value is None
+    # misaligned workspace pointer
+    assert L.jacobi_create(2, g, jb._arr64([1, 1]), 0, ctypes.c_void_p(16), 1 << 30, None,
+                           ctypes.byref(out)) == jb.JACOBI_E_INVAL
+    assert "aligned" in jb.jacobi_last_error()
+    # too small workspace
+    assert L.jacobi_create(2, g, jb._arr64([1, 1]), 0, ctypes.c_void_p(256), 16, None,
+                           ctypes.byref(out)) == jb.JACOBI_E_NOMEM
+    for name in ["jacobi_set_state", "jacobi_get_state", "jacobi_set_stream"]:
+        assert getattr(L, name)(None, None) == jb.JACOBI_E_INVAL
+    assert L.jacobi_sweep(None, 1) == jb.JACOBI_E_INVAL
+    assert L.jacobi_halo_exchange(None) == jb.JACOBI_E_INVAL
+    assert L.jacobi_residual(None, None) == jb.JACOBI_E_INVAL
+    assert L.jacobi_residual_async(None, None) == jb.JACOBI_E_INVAL
+    assert L.jacobi_solve(None, 1, 1, None) == jb.JACOBI_E_INVAL
+    assert L.jacobi_set_tuning(None, 1, 1, 0) == jb.JACOBI_E_INVAL
+    assert L.jacobi_destroy(None) == jb.JACOBI_OK
+
+
+def test_strerror_and_depths():
+    assert jb.jacobi_strerror(0) == "success"
+    assert "invalid" in jb.jacobi_strerror(jb.JACOBI_E_INVAL)
+    assert jb.jacobi_strerror(-99) == "unknown status"
+    assert jb.jacobi_max_depth(2, jb.JACOBI_F32) >= 4
+    assert jb.jacobi_max_depth(2, jb.JACOBI_F64) >= 2
+    assert jb.jacobi_max_depth(3, jb.JACOBI_F32) >= 1
+    with pytest.raises(jb.JacobiError):
+        jb.jacobi_max_depth(5, 0)
+
+
+def test_solver_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    with pytest.raises(RuntimeError, match="no GPU"):
+        jb.Solver((16, 16), (2, 2), torch.float32)
