@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark of the over-decomposed Jacobi sweep on one MI355X.
+
+Workload (one "step" = one whole solve, every step of the hot path):
+  2D 5-point Poisson Jacobi, 8192^2 interior, FP32 state and source, FP64
+  residual; source = sum of 16 Gaussians (seeded); zero Dirichlet ring; u_0 = 0;
+  over-decomposed into 16 x 16 blocks of 512^2 with one-cell halos;
+  1000 sweeps with the residual taken every 50 sweeps (and at 0).
+  Per step: scale the source into the blocks, scatter the initial state into
+  the blocks, 1000 sweeps (halo reads fused into the pass kernel, an explicit
+  halo exchange after each 50-sweep interval), 21 FP64 residuals, gather the
+  final state.  Inputs are resident in HBM before timing starts.
+
+Output: one JSON line (see the fields below).  `value` is GLUP/s (10^9 interior
+cell updates per second) of the whole step.  `roofline` describes the dominant
+kernel (the sweep pass kernel), timed live with HIP events on its own stream;
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Jacobi GLUP/s + HBM GB/s (% peak); adjoint/batched vs plain at 1e-5 rel err"
+N = 8192
+BLOCKS = (16, 16)
+SWEEPS = 1000
+CHECK_EVERY = 50
+HBM_PEAK_GBS = 8000.0
+# FP32 vector ALU peak without packed or fused instructions:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T ops/s
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+FLOPS_PER_UPDATE = 6  # (W+E), (S+N), sum, +b, *w  -> 4 adds + 1 add + 1 mul
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep2d_march_poisson8192.json")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2303_02543_amd", "csrc", "k_sweep.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--depth", type=int, default=0, help="temporal depth (0 = autotune)")
+    ap.add_argument("--rows", type=int, default=0, help="rows per tile (with --depth)")
+    ap.add_argument("--explicit-halo", action="store_true",
+                    help="exchange halos and sweep block-locally every sweep (depth 1)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample")
+    return ap.parse_args()
+
+
+def source_hash(path):
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_for(kernel_name, launches_alg_bytes):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None when
+    they are missing or were taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != source_hash(SWEEP_SOURCE):
+        return None
+    k = rec.get("kernels", {}).get(kernel_name)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(U0_np, f_np, h2, target_seconds):
+    """Time the FP64 oracle on the full grid for a bounded number of sweeps plus
+    one residual (a sample of the workload), return the JSON object."""
+    import numpy as np
+    import oracle
+    U = U0_np.astype(np.float64)
+    b = oracle.scale_source(f_np.astype(np.float64), h2, np.float64)
+    t0 = time.perf_counter()
+    U = oracle.sweep(U, b, 2)
+    dt2 = time.perf_counter() - t0
+    k = int(max(2, min(200, target_seconds / max(dt2 / 2, 1e-6))))
+    t0 = time.perf_counter()
+    U = oracle.sweep(U, b, k)
+    r = oracle.residual(U, b)
+    dt = time.perf_counter() - t0
+    cells = float(N) * N
+    return {
+        "value": round(cells * k / dt / 1e9, 4),
+        "unit": "GLUP/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": "FP64 oracle on the full %dx%d grid: %d sweeps + 1 residual (%.1f s)"
+                  % (N, N, k, dt),
+        "residual_check": r if math.isfinite(r) else None,
+    }
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the Jacobi library has no multi-GPU path "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2303_02543_amd as jb
+    import synthetic
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+
+    # inputs: drawn in FP64, rounded once to FP32, resident in HBM
+    f64 = synthetic.gaussian_sum(N, 2, 2)
+    f32 = f64.astype(np.float32)
+    U0_np = np.zeros((N + 2, N + 2), dtype=np.float32)
+    h2 = synthetic.spacing2(N)
+    f_dev = torch.from_numpy(f32).to(dev)
+    U0_dev = torch.from_numpy(U0_np).to(dev)
+    U_out = torch.empty_like(U0_dev)
+    nres = jb.residual_count(SWEEPS, CHECK_EVERY)
+    res = torch.empty(nres, dtype=torch.float64, device=dev)
+
+    s = jb.Solver((N, N), BLOCKS, torch.float32, device=dev)
+    if args.explicit_halo:
+        s.set_tuning(1, 0, jb.JACOBI_FLAG_EXPLICIT_HALO)
+    elif args.depth > 0:
+        s.set_tuning(args.depth, args.rows, 0)
+    else:
+        s.autotune(CHECK_EVERY, with_source=True)
+    depth, rows, flags = s.get_tuning()
+
+    def step():
+        s.set_source(f_dev, h2)            # scaled source into the blocks
+        s.set_state(U0_dev)                # scatter + halo fill
+        s.solve(SWEEPS, CHECK_EVERY, res)  # sweeps, halo exchange, residuals
+        s.get_state(U_out)                 # gather
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    s.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.profile(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    cells = float(N) * N
+    glups = cells * SWEEPS / (ms_per_step * 1e-3) / 1e9
+
+    # dominant kernel: the pass depth with the most kernel time
+    tot = s.profile_read(0)
+    best = None
+    for d in range(1, 17):
+        p = s.profile_read(d)
+        if p["launches"] and (best is None or p["ms"] > best[1]["ms"]):
+            best = (d, p)
+    d_dom, p = best
+    avg_ms = p["ms"] / p["launches"]
+    bytes_per_launch = p["alg_bytes"] / p["launches"]
+    flops_per_launch = FLOPS_PER_UPDATE * p["cell_updates"] / p["launches"]
+    hbm_gbs = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    alu_tops = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    if flags & jb.JACOBI_FLAG_EXPLICIT_HALO:
+        kname = "k_sweep_local<float, true>"
+    else:
+        kname = "k_sweep2d_march<float, %d, true>" % d_dom
+    traffic = traffic_for(kname, bytes_per_launch)
+    hbm_frac = hbm_gbs / HBM_PEAK_GBS
+    alu_frac = alu_tops / ALU_PEAK_TOPS
+    if hbm_frac >= alu_frac:
+        roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(hbm_frac, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(alu_tops, 3), "peak": round(ALU_PEAK_TOPS, 2),
+                "unit": "TFLOP/s", "frac": round(alu_frac, 4)}
+    roof["traffic"] = traffic
+    roof.update({
+        "kernel": kname,
+        "avg_launch_ms": round(avg_ms, 5),
+        "launches": p["launches"],
+        "alg_bytes_per_launch": bytes_per_launch,
+        "alg_flops_per_launch": flops_per_launch,
+        "hbm_gbs_alg": round(hbm_gbs, 1),
+        "alu_tops_alg": round(alu_tops, 3),
+        "kernel_share_of_step": round(tot["ms"] / (ms_per_step * args.steps), 4),
+    })
+
+    out = {
+        "metric": METRIC,
+        "value": round(glups, 3),
+        "unit": "GLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "2D 5-point Poisson Jacobi %dx%d FP32 (FP64 residual), 16-Gaussian "
+                        "source, %dx%d blocks of %dx%d, %d sweeps, residual every %d"
+                        % (N, N, BLOCKS[0], BLOCKS[1], N // BLOCKS[0], N // BLOCKS[1], SWEEPS,
+                           CHECK_EVERY),
+            "grid": [N, N], "blocks": list(BLOCKS), "sweeps": SWEEPS,
+            "check_every": CHECK_EVERY, "t_depth": depth, "rows": rows,
+            "explicit_halo": bool(flags & jb.JACOBI_FLAG_EXPLICIT_HALO),
+            "parallelism": "single GPU",
+        },
+        "roofline": roof,
+        "final_residual": float(res[-1].item()),
+        "residual_ratio": float(res[-1].item() / res[0].item()),
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(U0_np, f32, h2, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

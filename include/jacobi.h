@@ -151,6 +151,69 @@ int jacobi_get_tuning(jacobi_t h, int *t_depth, int *rows, int *flags);
 /* Largest temporal depth this build supports for the handle's ndim/dtype. */
 int jacobi_max_depth(int ndim, int dtype);
 
+/* --------------------------------------------------------------- adjoint */
+/*
+ * Reverse-mode derivative through K 2D sweeps (not in the paper; the
+ * differentiable form of the sweep).  One sweep is the affine map
+ * u_k = w (S u_{k-1} + B g + b), w = 1/4, with S the neighbour sum over the
+ * interior (zero ring, symmetric) and B moving each ring value into its one
+ * adjacent interior node.  Given lam_K = dL/du_K, the adjoint runs
+ *     for k = K .. 1:  Gb += w lam_k;   lam_{k-1} = w S lam_k   (zero ring)
+ * and yields dL/db = Gb, dL/df = h^2 Gb, dL/du_0 = lam_0 and, for each
+ * non-corner ring node q, dL/dg_q = Gb[p(q)] (p(q) its adjacent interior
+ * node; corners 0).  The lam sweep is the 5-point sweep with a zero ring and
+ * no source; Gb is accumulated in FP64 in the order k = K, K-1, ..., 1.
+ * 2D only (JACOBI_E_UNSUPPORTED for 3D handles).
+ */
+
+/* Start an adjoint run: the handle's state becomes lam (device full state
+ * array of the handle dtype whose interior holds dL/du_K; its ring is read as
+ * zero), and grad_b (device FP64 interior array, n_y x n_x, x fastest,
+ * caller-owned) is zeroed and becomes the accumulator.  grad_b must stay
+ * valid until jacobi_adjoint_end. */
+int jacobi_adjoint_begin(jacobi_t h, const void *lam, double *grad_b);
+
+/* n_iter >= 0 adjoint sweeps (backward through n_iter forward sweeps),
+ * grouped into passes like jacobi_sweep.  Segments may be issued in any
+ * chunking (checkpointing): results do not depend on it.  Afterwards
+ * jacobi_get_state returns lam with a zero ring. */
+int jacobi_adjoint_sweep(jacobi_t h, int64_t n_iter);
+
+/* Finish: grad_f (device FP64 interior array, may be NULL, may alias
+ * grad_b) = h2 * grad_b; grad_ring (device FP64 full (n_y+2) x (n_x+2) array,
+ * may be NULL) = dL/dg on non-corner ring nodes, 0 on corners and interior. */
+int jacobi_adjoint_end(jacobi_t h, double h2, double *grad_f, double *grad_ring);
+
+/* ------------------------------------------------------------ profiling */
+
+/* Start (enable != 0) or stop recording a pair of HIP events on the handle's
+ * stream around every sweep-kernel launch (the pass kernels of jacobi_sweep
+ * and jacobi_solve).  Enabling discards earlier records.  Recording adds no
+ * device work besides the event markers. */
+int jacobi_profile(jacobi_t h, int enable);
+
+/* Summarise the records: launches of passes of `depth` sweeps (0 = all
+ * launches).  Outputs: summed kernel time in milliseconds, number of
+ * launches, cell updates performed (interior cells times sweeps) and
+ * algorithmic HBM bytes (per pass: one read of the state and the source and
+ * one write of the state per interior cell).  Synchronises the stream.  Any
+ * output pointer may be NULL. */
+int jacobi_profile_read(jacobi_t h, int depth, double *ms, int64_t *launches,
+                        double *cell_updates, double *alg_bytes);
+
+/* Pick the sweep schedule by timing.  Runs jacobi_sweep(n_sweeps) on the
+ * handle's own buffers for each candidate temporal depth and tile height
+ * (plus the explicit-halo schedule) and keeps the fastest; every candidate
+ * computes identical results, so the choice never changes any output.
+ * with_source: time the Poisson (1) or Laplace (0) kernels.  The buffers'
+ * contents are used as scratch: the handle is left without a state
+ * (JACOBI_E_STATE until jacobi_set_state).  Synchronises the stream.
+ * If the environment variable JACOBI_TUNE_CACHE names a file, results are
+ * looked up in and appended to it (one line per problem shape).
+ * Outputs (may be NULL): the chosen depth, rows and flags. */
+int jacobi_autotune(jacobi_t h, int64_t n_sweeps, int with_source, int *t_depth, int *rows,
+                    int *flags);
+
 /* --------------------------------------------------------------- errors */
 const char *jacobi_strerror(int status);
 const char *jacobi_last_error(void);

@@ -65,8 +65,15 @@ def lib():
             getattr(L, "orc_window3d_" + suf).argtypes = [I64, I64, I64, P, P, I64, I64, I64, I64,
                                                           I64, I64, I64, P]
         L.orc_adjoint2d_f64.argtypes = [I64, I64, I64, P, P, P, P]
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = ctypes.c_int
         _LIB = L
     return _LIB
+
+
+def num_threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().orc_num_threads())
 
 
 def _suffix(dtype):

@@ -16,6 +16,7 @@
  * summed serially in index order, so results do not depend on thread count.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -31,6 +32,9 @@
 #include "jacobi_oracle_body.h"
 #undef REAL
 #undef SUF
+
+/* Threads an OpenMP region of the oracle uses. */
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 /*
  * Reverse-mode derivative of L = 1/2 * sum_interior (u_K - t)^2 through K

@@ -54,6 +54,13 @@ _SIGNATURES = {
     "jacobi_set_tuning": [_P, _I, _I, _I],
     "jacobi_get_tuning": [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)],
     "jacobi_max_depth": [_I, _I],
+    "jacobi_adjoint_begin": [_P, _P, _P],
+    "jacobi_adjoint_sweep": [_P, _I64],
+    "jacobi_adjoint_end": [_P, _D, _P, _P],
+    "jacobi_profile": [_P, _I],
+    "jacobi_profile_read": [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(_I64),
+                            ctypes.POINTER(_D), ctypes.POINTER(_D)],
+    "jacobi_autotune": [_P, _I64, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)],
     "jacobi_strerror": [_I],
     "jacobi_last_error": [],
 }
@@ -200,6 +207,39 @@ def jacobi_max_depth(ndim, dtype):
     return v
 
 
+def jacobi_adjoint_begin(h, lam_ptr, grad_b_ptr):
+    _check(lib().jacobi_adjoint_begin(h, lam_ptr, grad_b_ptr))
+
+
+def jacobi_adjoint_sweep(h, n_iter):
+    _check(lib().jacobi_adjoint_sweep(h, int(n_iter)))
+
+
+def jacobi_adjoint_end(h, h2, grad_f_ptr, grad_ring_ptr):
+    _check(lib().jacobi_adjoint_end(h, float(h2), grad_f_ptr, grad_ring_ptr))
+
+
+def jacobi_profile(h, enable):
+    _check(lib().jacobi_profile(h, 1 if enable else 0))
+
+
+def jacobi_profile_read(h, depth=0):
+    """Returns dict(ms, launches, cell_updates, alg_bytes) over the recorded
+    launches of passes of `depth` sweeps (0 = all)."""
+    ms, n, up, by = _D(), _I64(), _D(), _D()
+    _check(lib().jacobi_profile_read(h, int(depth), ctypes.byref(ms), ctypes.byref(n),
+                                     ctypes.byref(up), ctypes.byref(by)))
+    return dict(ms=ms.value, launches=n.value, cell_updates=up.value, alg_bytes=by.value)
+
+
+def jacobi_autotune(h, n_sweeps, with_source):
+    """Returns the chosen (t_depth, rows, flags); leaves the handle without a state."""
+    d, r, f = _I(), _I(), _I()
+    _check(lib().jacobi_autotune(h, int(n_sweeps), 1 if with_source else 0, ctypes.byref(d),
+                                 ctypes.byref(r), ctypes.byref(f)))
+    return d.value, r.value, f.value
+
+
 def jacobi_strerror(status):
     return lib().jacobi_strerror(int(status)).decode()
 
@@ -312,6 +352,41 @@ class Solver:
 
     def get_tuning(self):
         return jacobi_get_tuning(self.h)
+
+    def adjoint(self, lam_K, n_iter, h2, chunk=None, checkpoints=None):
+        """Reverse sweeps: from dL/du_K (full state tensor, ring ignored) return
+        (dL/df FP64 interior, dL/dU0 as a full FP64 array: ring = dL/dg,
+        interior = dL/du_0).  chunk: sweeps per adjoint segment (checkpoint
+        interval); checkpoints: optional list that receives lam at every
+        segment boundary (device tensors)."""
+        import torch
+        self._check_tensor(lam_K, self.state_shape, "lam_K")
+        gb = torch.empty(self.interior_shape, dtype=torch.float64, device=self.device)
+        ring = torch.empty(self.state_shape, dtype=torch.float64, device=self.device)
+        jacobi_adjoint_begin(self.h, _ptr(lam_K), _ptr(gb))
+        chunk = int(n_iter) if not chunk else int(chunk)
+        left = int(n_iter)
+        while left > 0:
+            step = min(chunk, left)
+            jacobi_adjoint_sweep(self.h, step)
+            left -= step
+            if checkpoints is not None:
+                checkpoints.append(self.get_state())
+        jacobi_adjoint_end(self.h, h2, _ptr(gb), _ptr(ring))
+        lam0 = self.get_state()
+        grad_u0 = ring
+        grad_u0[(slice(1, -1),) * self.ndim] = lam0[(slice(1, -1),) * self.ndim].to(torch.float64)
+        return gb, grad_u0
+
+    def profile(self, enable=True):
+        jacobi_profile(self.h, enable)
+
+    def profile_read(self, depth=0):
+        return jacobi_profile_read(self.h, depth)
+
+    def autotune(self, n_sweeps, with_source=True):
+        """Pick the fastest bit-neutral schedule; the state must be set afterwards."""
+        return jacobi_autotune(self.h, n_sweeps, with_source)
 
     def layout(self):
         return jacobi_get_layout(self.h)

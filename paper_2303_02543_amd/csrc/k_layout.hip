@@ -20,7 +20,7 @@ namespace jac {
 template <typename R>
 __global__ __launch_bounds__(256) void k_scatter(Geom g, const R *__restrict__ u,
                                                  R *__restrict__ s0, R *__restrict__ s1,
-                                                 int64_t total) {
+                                                 int64_t total, int zero_ring) {
     const int64_t nx2 = g.n[0] + 2, ny2 = g.n[1] + 2;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -29,7 +29,9 @@ __global__ __launch_bounds__(256) void k_scatter(Geom g, const R *__restrict__ u
         const int y = (int)(rest % ny2) - 1;
         const int z = (int)(rest / ny2) - 1;
         const int64_t off = state_offset(g, x, y, z);
-        const R v = u[i];
+        const bool ring = x < 0 || x >= g.n[0] || y < 0 || y >= g.n[1] ||
+                          (g.ndim == 3 && (z < 0 || z >= g.n[2]));
+        const R v = (zero_ring && ring) ? (R)0 : u[i];
         s0[off] = v;
         s1[off] = v;
     }
@@ -115,10 +117,66 @@ static inline int grid_for(int64_t total) {
 }
 
 template <typename R>
-hipError_t launch_scatter(const Geom &g, const void *u, void *s0, void *s1, hipStream_t st) {
+hipError_t launch_scatter(const Geom &g, const void *u, void *s0, void *s1, bool zero_ring,
+                          hipStream_t st) {
     const int64_t total = (int64_t)(g.n[0] + 2) * (g.n[1] + 2) * (g.ndim == 3 ? g.n[2] + 2 : 1);
     hipLaunchKernelGGL(k_scatter<R>, dim3(grid_for(total)), dim3(256), 0, st, g,
-                       (const R *)u, (R *)s0, (R *)s1, total);
+                       (const R *)u, (R *)s0, (R *)s1, total, zero_ring ? 1 : 0);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_fill_f64(double *__restrict__ p, double v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+// End of a 2D adjoint run.  gb: FP64 interior accumulator dL/db (n_y x n_x).
+// Two stream-ordered kernels so that grad_f may alias gb:
+//  1. grad_ring (full (n_y+2) x (n_x+2) array): each non-corner ring node gets
+//     gb at the one interior node next to it (dL/dg_q = sum_k w lam_k[p(q)]
+//     = gb[p(q)]); corners and interior nodes get 0;
+//  2. grad_f (interior) = h2 * gb.
+__global__ __launch_bounds__(256) void k_adjoint_ring(int nx, int ny, const double *__restrict__ gb,
+                                                      double *__restrict__ grad_ring,
+                                                      int64_t total) {
+    const int64_t nx2 = nx + 2;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx2) - 1;
+        const int y = (int)(i / nx2) - 1;
+        const bool inx = x >= 0 && x < nx, iny = y >= 0 && y < ny;
+        double v = 0.0;
+        if (inx && !iny) v = gb[(int64_t)(y < 0 ? 0 : ny - 1) * nx + x];
+        if (iny && !inx) v = gb[(int64_t)y * nx + (x < 0 ? 0 : nx - 1)];
+        grad_ring[i] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scale_f64(const double *gb, double h2, double *out,
+                                                   int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = h2 * gb[i];
+}
+
+hipError_t launch_adjoint_finish(const Geom &g, const double *gb, double h2, double *grad_f,
+                                 double *grad_ring, hipStream_t st) {
+    if (grad_ring) {
+        const int64_t total = (int64_t)(g.n[0] + 2) * (g.n[1] + 2);
+        hipLaunchKernelGGL(k_adjoint_ring, dim3(grid_for(total)), dim3(256), 0, st, g.n[0],
+                           g.n[1], gb, grad_ring, total);
+    }
+    if (grad_f) {
+        const int64_t n = (int64_t)g.n[0] * g.n[1];
+        hipLaunchKernelGGL(k_scale_f64, dim3(grid_for(n)), dim3(256), 0, st, gb, h2, grad_f, n);
+    }
     return hipGetLastError();
 }
 
@@ -155,8 +213,10 @@ hipError_t launch_halo_exchange(const Geom &g, void *s, hipStream_t st) {
     return hipGetLastError();
 }
 
-template hipError_t launch_scatter<float>(const Geom &, const void *, void *, void *, hipStream_t);
-template hipError_t launch_scatter<double>(const Geom &, const void *, void *, void *, hipStream_t);
+template hipError_t launch_scatter<float>(const Geom &, const void *, void *, void *, bool,
+                                          hipStream_t);
+template hipError_t launch_scatter<double>(const Geom &, const void *, void *, void *, bool,
+                                           hipStream_t);
 template hipError_t launch_gather<float>(const Geom &, const void *, void *, hipStream_t);
 template hipError_t launch_gather<double>(const Geom &, const void *, void *, hipStream_t);
 template hipError_t launch_scale_source<float>(const Geom &, const void *, void *, double, hipStream_t);

@@ -13,21 +13,11 @@
 // order never depends on scheduling, so repeated calls give identical bits.
 #include <hip/hip_runtime.h>
 
+#include "device_util.h"
 #include "jacobi_internal.h"
 #include "kernels.h"
 
 namespace jac {
-
-template <typename R, int V>
-struct alignas(16) RChunk {
-    R v[V];
-};
-
-__device__ __forceinline__ double wave_sum(double a) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-    return a;
-}
 
 template <typename R, bool SRC>
 __global__ __launch_bounds__(256) void k_residual(Geom g, const R *__restrict__ u,
@@ -35,7 +25,7 @@ __global__ __launch_bounds__(256) void k_residual(Geom g, const R *__restrict__ 
                                                   double *__restrict__ partials, int64_t total,
                                                   int cpr) {
     constexpr int V = 16 / sizeof(R);
-    using C = RChunk<R, V>;
+    using C = Chunk<R, V>;
     const int nx = g.n[0], ny = g.n[1];
     const double c2d = 2.0 * g.ndim;
     double acc = 0.0;
@@ -89,6 +79,11 @@ __global__ __launch_bounds__(256) void k_residual_final(const double *__restrict
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = sqrt(sh[0]);
+}
+
+hipError_t launch_residual_final(const double *partials, int n, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, st, partials, n, out);
+    return hipGetLastError();
 }
 
 template <typename R>

@@ -7,8 +7,13 @@
 
 namespace jac {
 
+// zero_ring: write 0 instead of the ring values (the adjoint state's ring).
 template <typename R>
-hipError_t launch_scatter(const Geom &g, const void *u, void *s0, void *s1, hipStream_t st);
+hipError_t launch_scatter(const Geom &g, const void *u, void *s0, void *s1, bool zero_ring,
+                          hipStream_t st);
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t st);
+hipError_t launch_adjoint_finish(const Geom &g, const double *gb, double h2, double *grad_f,
+                                 double *grad_ring, hipStream_t st);
 template <typename R>
 hipError_t launch_gather(const Geom &g, const void *s, void *u, hipStream_t st);
 template <typename R>
@@ -22,12 +27,26 @@ hipError_t launch_sweep_local(const Geom &g, const void *uin, void *uout, const 
                               hipStream_t st);
 
 // `depth` sweeps in one pass over the whole 2D grid, reading face neighbours'
-// cells from their owning blocks.  depth must be one of march2d_depths().
+// cells from their owning blocks.  uout may be NULL (no output: residual
+// only).  If res is not NULL, the FP64 residual of the input state is
+// accumulated and one partial per work item is written to res[0 .. nwork);
+// k_residual_final then sums them.  If gacc is not NULL the pass is an
+// adjoint pass: b and res must be NULL, the state's ring must be zero, and
+// w * (the pass's input and its first depth-1 levels) is added, in that
+// order, to the FP64 interior array gacc (n_y x n_x).  depth must be one of
+// march2d_depths().
 template <typename R>
 hipError_t launch_sweep2d_march(const Geom &g, const void *uin, void *uout, const void *b,
-                                int depth, int rows, hipStream_t st);
+                                double *res, double *gacc, int depth, int rows, hipStream_t st,
+                                int64_t *nwork);
+// Work items (waves) of one march launch; -1 for an unknown depth.
+template <typename R>
+int64_t march2d_work_items(const Geom &g, int depth, int rows);
 // Depths compiled for the 2D march kernel, ascending; returns the count.
 int march2d_depths(int dtype, const int **list);
+
+// Sum n partials in a fixed order and write sqrt(total) to *out.
+hipError_t launch_residual_final(const double *partials, int n, double *out, hipStream_t st);
 
 // FP64 residual: per-workgroup partial sums into `partials` (kResidualGroups
 // doubles), then one workgroup sums them in a fixed order and writes

@@ -96,6 +96,9 @@ def test_null_pointers_and_handles_rejected():
     assert L.jacobi_residual_async(None, None) == jb.JACOBI_E_INVAL
     assert L.jacobi_solve(None, 1, 1, None) == jb.JACOBI_E_INVAL
     assert L.jacobi_set_tuning(None, 1, 1, 0) == jb.JACOBI_E_INVAL
+    assert L.jacobi_profile(None, 1) == jb.JACOBI_E_INVAL
+    assert L.jacobi_profile_read(None, 0, None, None, None, None) == jb.JACOBI_E_INVAL
+    assert L.jacobi_autotune(None, 10, 1, None, None, None) == jb.JACOBI_E_INVAL
     assert L.jacobi_destroy(None) == jb.JACOBI_OK
 
 

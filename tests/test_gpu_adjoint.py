@@ -1,0 +1,145 @@
+"""Adjoint (reverse-mode) parity: the device adjoint through the C ABI and the
+torch.autograd wrapper against the FP64 oracle adjoint, its finite
+differences, and invariance in the checkpoint interval."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+from gpu_util import bits_equal, norm_rel_err
+
+pytestmark = pytest.mark.gpu
+
+RNG = np.random.default_rng(99)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def device_adjoint(lamK_full, K, h2, blocks, dtype, device, depth=0, rows=0, chunk=None):
+    import torch
+    import paper_2303_02543_amd as jb
+    tdt = torch.float32 if dtype == np.float32 else torch.float64
+    ny, nx = lamK_full.shape[0] - 2, lamK_full.shape[1] - 2
+    s = jb.Solver((nx, ny), blocks, tdt, device=device)
+    try:
+        s.set_tuning(depth, rows, 0)
+        lam = torch.from_numpy(np.ascontiguousarray(lamK_full, dtype=dtype)).to(device)
+        gf, gU0 = s.adjoint(lam, K, h2, chunk=chunk)
+        torch.cuda.synchronize()
+        return gf.cpu().numpy(), gU0.cpu().numpy()
+    finally:
+        s.close()
+
+
+CASES = [(37, 29, 3, 4, 13), (130, 70, 2, 3, 40), (8, 8, 1, 1, 5), (1, 1, 1, 1, 3), (300, 9, 4, 1, 21)]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_adjoint_fp64_bit_exact(device, case):
+    """FP64 device adjoint == FP64 oracle adjoint bit for bit (same order of
+    accumulation k = K..1), for every chunking of the reverse sweeps."""
+    nx, ny, bx, by, K = case
+    h2 = synthetic.spacing2(max(nx, ny))
+    lamK = RNG.standard_normal((ny, nx))
+    full = RNG.standard_normal((ny + 2, nx + 2))   # ring garbage must be ignored
+    full[1:-1, 1:-1] = lamK
+    Gb, Gring, lam0 = oracle.adjoint2d(lamK, K)
+    want_f = h2 * Gb
+    for chunk in (None, 1, 7):
+        say("adjoint fp64 case=%s chunk=%s" % (case, chunk))
+        gf, gU0 = device_adjoint(full, K, h2, (bx, by), np.float64, device, chunk=chunk)
+        assert bits_equal(gf, want_f), "dL/df"
+        ring = gU0.copy()
+        ring[1:-1, 1:-1] = 0.0
+        assert bits_equal(ring, Gring), "dL/dg"
+        assert bits_equal(np.ascontiguousarray(gU0[1:-1, 1:-1]), lam0), "dL/du0"
+
+
+def test_adjoint_fp32_within_1e5(device):
+    n, K = 255, 300
+    h2 = synthetic.spacing2(n)
+    lamK = synthetic.gaussian_sum(n, 2, 6).astype(np.float32)
+    full = np.zeros((n + 2, n + 2), dtype=np.float32)
+    full[1:-1, 1:-1] = lamK
+    Gb, Gring, lam0 = oracle.adjoint2d(lamK.astype(np.float64), K)
+    gf, gU0 = device_adjoint(full, K, h2, (2, 2), np.float32, device, chunk=50)
+    e_f = np.max(np.abs(gf - h2 * Gb)) / np.max(np.abs(h2 * Gb))
+    ring = gU0.copy()
+    ring[1:-1, 1:-1] = 0
+    e_g = np.max(np.abs(ring - Gring)) / np.max(np.abs(Gring))
+    e_l = np.max(np.abs(gU0[1:-1, 1:-1] - lam0)) / np.max(np.abs(lam0))
+    say("adjoint fp32 errors f=%.2e g=%.2e u0=%.2e" % (e_f, e_g, e_l))
+    assert e_f <= 1e-5 and e_g <= 1e-5 and e_l <= 1e-5
+
+
+def test_autograd_matches_oracle_and_fd(device):
+    """Loss 1/2 |u_K - t|^2 through JacobiK (FP64): gradients equal the
+    oracle's FP64 gradients bit for bit, and central finite differences."""
+    import torch
+    import paper_2303_02543_amd as jb
+    from paper_2303_02543_amd.autograd import JacobiK
+    n, K = 41, 30
+    h2 = synthetic.spacing2(n)
+    U0 = synthetic.ring_values(n, 2, 7)
+    f = synthetic.gaussian_sum(n, 2, 5)
+    t = synthetic.gaussian_sum(n, 2, 6) * 1e-3
+    s = jb.Solver((n, n), (2, 3), torch.float64, device=device)
+    try:
+        fT = torch.from_numpy(f).to(device).requires_grad_(True)
+        UT = torch.from_numpy(U0).to(device).requires_grad_(True)
+        tT = torch.from_numpy(t).to(device)
+        uK = JacobiK.apply(fT, UT, s, K, h2, 7)
+        loss = 0.5 * ((uK[1:-1, 1:-1] - tT) ** 2).sum()
+        loss.backward()
+        gf = fT.grad.cpu().numpy()
+        gU = UT.grad.cpu().numpy()
+    finally:
+        s.close()
+    L, dLdf, dLdU0 = oracle.gradients2d(U0, f, h2, t, K)
+    assert math.isclose(float(loss), L, rel_tol=1e-12)
+    assert bits_equal(gf, dLdf)
+    assert bits_equal(gU, dLdU0)
+    f_idx, g_idx = synthetic.fd_picks(n, count=6, seed=8)
+    for idx in f_idx:
+        fd = oracle.fd_grad_source(U0, f, h2, t, K, idx, 1e-3)
+        assert math.isclose(fd, gf[idx], rel_tol=1e-6, abs_tol=1e-14)
+    for idx in g_idx:
+        fd = oracle.fd_grad_state(U0, f, h2, t, K, idx, 1e-3)
+        assert math.isclose(fd, gU[idx], rel_tol=1e-6, abs_tol=1e-14)
+
+
+def test_checkpoint_interval_invariance_and_checkpoints(device):
+    """Gradients are bit-identical for C in {1, 7, 50, K}; the forward
+    checkpoints equal the oracle's states after 0, C, 2C, ... sweeps."""
+    import torch
+    import paper_2303_02543_amd as jb
+    from paper_2303_02543_amd.autograd import JacobiK
+    n, K = 64, 100
+    h2 = synthetic.spacing2(n)
+    U0 = synthetic.ring_values(n, 2, 7).astype(np.float32)
+    f = synthetic.gaussian_sum(n, 2, 5).astype(np.float32)
+    t = (synthetic.gaussian_sum(n, 2, 6) * 1e-3).astype(np.float32)
+    grads = []
+    s = jb.Solver((n, n), (2, 2), torch.float32, device=device)
+    try:
+        for C in (1, 7, 50, K):
+            fT = torch.from_numpy(f).to(device).requires_grad_(True)
+            UT = torch.from_numpy(U0).to(device).requires_grad_(True)
+            uK = JacobiK.apply(fT, UT, s, K, h2, C)
+            ckpts = uK.grad_fn.checkpoints
+            loss = 0.5 * ((uK[1:-1, 1:-1] - torch.from_numpy(t).to(device)) ** 2).sum()
+            loss.backward()
+            grads.append((fT.grad.cpu().numpy(), UT.grad.cpu().numpy()))
+            b32 = oracle.scale_source(f, h2, np.float32)
+            for i, ck in enumerate(ckpts):
+                want = oracle.sweep(U0, b32, i * C)
+                assert bits_equal(ck.cpu().numpy(), want), "checkpoint %d (C=%d)" % (i, C)
+    finally:
+        s.close()
+    for gf, gU in grads[1:]:
+        assert bits_equal(gf, grads[0][0]) and bits_equal(gU, grads[0][1])
