@@ -44,11 +44,10 @@ struct M2 {
     static constexpr int L0 = A0 / V;                         // first output lane
     static constexpr int L1 = (A0 + OW) / V;                  // one past the last output lane
     static constexpr int U = 12;                              // steps per unrolled group
-    static constexpr int RB = T + 2 <= 3 ? 3 : T + 2 <= 4 ? 4 : T + 2 <= 6 ? 6 : 12;
+    static constexpr int RB = T + 2;                          // source rows r-T .. r+1 (LDS)
     static constexpr int NL = T > 1 ? T - 1 : 1;              // stored levels 1..T-1
     // adjoint accumulator rows r-T+1 .. r+1
     static constexpr int RA = T + 1 <= 2 ? 2 : T + 1 <= 3 ? 3 : T + 1 <= 4 ? 4 : T + 1 <= 6 ? 6 : 12;
-    static_assert(T + 2 <= 12, "source ring holds rows r-T .. r+1");
 };
 
 // Row cursor: global row y, its block row / local row, and the element
@@ -92,7 +91,6 @@ struct MRegs {
     R l0[4][S::V];           // level-0 rows, slot = row mod 4 (r-2 .. r+1)
     R e0[4];                 // level-0 cell just outside the strip (lanes 0, 63)
     R lv[S::NL][3][S::V];    // levels 1..T-1, slot = step mod 3
-    R bq[S::RB][S::V];       // source rows r-T .. r+1
     double ga[S::RA][S::V];  // adjoint: FP64 accumulator rows r-T+1 .. r+1
     double acc;              // residual partial sum (level 1)
 };
@@ -104,16 +102,17 @@ struct MLane {
     bool st[8];                      // per-element: interior output column (ring strips)
     bool out_lane;                   // lane holds output columns
     int c;                           // global column of the lane's first element
+    void *bs;                        // this lane's slot 0 of the wave's LDS source ring
     int oy0, oy1, r1;
 };
 
 // Issue the loads of row lc.y into level-0 slot SL, source slot SB and (adjoint
 // pass) accumulator slot SA, then advance the cursor.
-template <typename R, int T, int MODE, bool RINGX, int SL, int SB, int SA>
+template <typename R, int T, int MODE, bool RINGX, int SL, int SA>
 __device__ __forceinline__ void m2_load(const Geom &g, const R *__restrict__ uin,
                                         const R *__restrict__ bsrc,
                                         const double *__restrict__ gacc, const MLane &L,
-                                        MRegs<R, T> &m, Cur &lc) {
+                                        MRegs<R, T> &m, Cur &lc, const int bslot) {
     constexpr int V = M2<R, T>::V;
     constexpr bool SRC = MODE == MODE_POISSON;
     using C = Chunk<R, V>;
@@ -147,17 +146,12 @@ __device__ __forceinline__ void m2_load(const Geom &g, const R *__restrict__ uin
 #pragma unroll
                 for (int v = 0; v < V; ++v) c.v[v] = (R)0;
             }
-#pragma unroll
-            for (int v = 0; v < V; ++v) m.bq[SB][v] = c.v[v];
+            static_cast<C *>(L.bs)[bslot * 64] = c;
         }
     } else {
 #pragma unroll
         for (int v = 0; v < V; ++v) m.l0[SL][v] = (R)0;
         m.e0[SL] = (R)0;
-        if constexpr (SRC) {
-#pragma unroll
-            for (int v = 0; v < V; ++v) m.bq[SB][v] = (R)0;
-        }
     }
     lc.advance(g);
 }
@@ -194,7 +188,7 @@ template <typename R, int T, int MODE, bool RINGX, int J, int S>
 __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
                                          double *__restrict__ gacc, const bool res,
                                          const MLane &L, MRegs<R, T> &m, const int r,
-                                         const Cur &sc) {
+                                         const Cur &sc, const int sr) {
     using M = M2<R, T>;
     constexpr int V = M::V;
     constexpr bool SRC = MODE == MODE_POISSON;
@@ -216,7 +210,13 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
                 dn[v] = m.lv[S - 2][J % 3][v];
             }
         }
-        constexpr int BS = (J - S + 2 * M::RB) % M::RB;  // source row r - S
+        R bv[V];  // source row r - S from the wave's LDS ring
+        if constexpr (SRC) {
+            const int slot = sr - S < 0 ? sr - S + M::RB : sr - S;
+            const Chunk<R, V> c = static_cast<const Chunk<R, V> *>(L.bs)[slot * 64];
+#pragma unroll
+            for (int v = 0; v < V; ++v) bv[v] = c.v[v];
+        }
         R out[V];
         if (y >= 0 && y < ny) {
             R eo = (R)0;
@@ -232,7 +232,7 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
                 const R sum = (Wv + Ev) + (up[v] + dn[v]);
                 R o;
                 if constexpr (SRC)
-                    o = (sum + m.bq[BS][v]) * w;
+                    o = (sum + bv[v]) * w;
                 else
                     o = sum * w;
                 if constexpr (S == 1) {
@@ -240,8 +240,8 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
                         // residual of the input state, FP64 from widened values
                         const double sd =
                             ((double)Wv + (double)Ev) + ((double)up[v] + (double)dn[v]);
-                        const double bv = SRC ? (double)m.bq[BS][v] : 0.0;
-                        const double rr = bv - (4.0 * (double)cen[v] - sd);
+                        const double bd = SRC ? (double)bv[v] : 0.0;
+                        const double rr = bd - (4.0 * (double)cen[v] - sd);
                         const bool mine = RINGX ? L.st[v] : L.out_lane;
                         m.acc += mine ? rr * rr : 0.0;
                     }
@@ -276,7 +276,7 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
                 }
             }
         }
-        m2_level<R, T, MODE, RINGX, J, S + 1>(g, uout, gacc, res, L, m, r, sc);
+        m2_level<R, T, MODE, RINGX, J, S + 1>(g, uout, gacc, res, L, m, r, sc, sr);
     }
 }
 
@@ -285,7 +285,7 @@ __device__ __forceinline__ void m2_steps(const Geom &g, const R *__restrict__ ui
                                          R *__restrict__ uout, const R *__restrict__ bsrc,
                                          double *__restrict__ gacc, const bool res,
                                          const MLane &L, MRegs<R, T> &m, const int base, Cur &lc,
-                                         Cur &sc) {
+                                         Cur &sc, int &sr) {
     using M = M2<R, T>;
     constexpr int V = M::V;
     if constexpr (J < M::U) {
@@ -293,9 +293,10 @@ __device__ __forceinline__ void m2_steps(const Geom &g, const R *__restrict__ ui
         if (r > L.r1) return;
         // row r+1 goes into the slots rows r-3 (state), r+1-RB (source) and
         // r+1-RA (accumulator) held
+        const int sr1 = sr + 1 == M::RB ? 0 : sr + 1;  // LDS source slot of row r+1
         if (r + 1 <= L.r1)
-            m2_load<R, T, MODE, RINGX, (J + 1) % 4, (J + 1) % M::RB, (J + 1) % M::RA>(
-                g, uin, bsrc, gacc, L, m, lc);
+            m2_load<R, T, MODE, RINGX, (J + 1) % 4, (J + 1) % M::RA>(g, uin, bsrc, gacc, L, m, lc,
+                                                                     sr1);
         if constexpr (MODE == MODE_ADJOINT) {
             // level 0 of row r (the pass's input) is the first term added
             R v0[V];
@@ -303,9 +304,10 @@ __device__ __forceinline__ void m2_steps(const Geom &g, const R *__restrict__ ui
             for (int v = 0; v < V; ++v) v0[v] = m.l0[J % 4][v];
             m2_accumulate<R, T, MODE, RINGX, J % M::RA, T == 1>(g, gacc, L, m, r, v0);
         }
-        m2_level<R, T, MODE, RINGX, J, 1>(g, uout, gacc, res, L, m, r, sc);
+        m2_level<R, T, MODE, RINGX, J, 1>(g, uout, gacc, res, L, m, r, sc, sr);
         sc.advance(g);
-        m2_steps<R, T, MODE, RINGX, J + 1>(g, uin, uout, bsrc, gacc, res, L, m, base, lc, sc);
+        sr = sr1;
+        m2_steps<R, T, MODE, RINGX, J + 1>(g, uin, uout, bsrc, gacc, res, L, m, base, lc, sc, sr);
     }
 }
 
@@ -329,10 +331,6 @@ __device__ __forceinline__ void m2_body(const Geom &g, const R *__restrict__ uin
 #pragma unroll
             for (int v = 0; v < S::V; ++v) m.lv[s][k][v] = (R)0;
 #pragma unroll
-    for (int k = 0; k < S::RB; ++k)
-#pragma unroll
-        for (int v = 0; v < S::V; ++v) m.bq[k][v] = (R)0;
-#pragma unroll
     for (int k = 0; k < S::RA; ++k)
 #pragma unroll
         for (int v = 0; v < S::V; ++v) m.ga[k][v] = 0.0;
@@ -340,10 +338,11 @@ __device__ __forceinline__ void m2_body(const Geom &g, const R *__restrict__ uin
     Cur lc, sc;
     lc.init(g, r0);
     sc.init(g, r0 - T);
-    m2_load<R, T, MODE, RINGX, 0, 0, 0>(g, uin, bsrc, gacc, L, m, lc);  // row r0 -> slot 0
+    m2_load<R, T, MODE, RINGX, 0, 0>(g, uin, bsrc, gacc, L, m, lc, 0);  // row r0 -> slot 0
     const bool want_res = res != nullptr;
+    int sr = 0;  // LDS source slot of the current row
     for (int base = r0; base <= L.r1; base += S::U)
-        m2_steps<R, T, MODE, RINGX, 0>(g, uin, uout, bsrc, gacc, want_res, L, m, base, lc, sc);
+        m2_steps<R, T, MODE, RINGX, 0>(g, uin, uout, bsrc, gacc, want_res, L, m, base, lc, sc, sr);
     if (want_res) {
         const double a = wave_sum(m.acc);
         if ((threadIdx.x & 63) == 0) res[wid] = a;
@@ -362,6 +361,8 @@ __global__ __launch_bounds__(256) void k_march2d(Geom g, const R *__restrict__ u
     using S = M2<R, T>;
     constexpr bool SRC = MODE == MODE_POISSON;
     constexpr int V = S::V;
+    // per wave: a ring of RB source rows, one 16-byte chunk per lane each
+    __shared__ Chunk<R, V> bsm[SRC ? 4 * S::RB * 64 : 1];
     const int lane = threadIdx.x & 63;
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int wid = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -370,6 +371,7 @@ __global__ __launch_bounds__(256) void k_march2d(Geom g, const R *__restrict__ u
     const int nx = g.n[0], ny = g.n[1];
     const int a = strip * S::OW - S::A0;  // first column held by the strip
     MLane L;
+    L.bs = SRC ? (void *)&bsm[(threadIdx.x >> 6) * S::RB * 64 + lane] : nullptr;
     L.oy0 = seg * rows;
     L.oy1 = L.oy0 + rows < ny ? L.oy0 + rows : ny;
     L.r1 = L.oy1 - 1 + T;
