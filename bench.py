@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 FLOPS_PER_UPDATE = 6  # (W+E), (S+N), sum, +b, *w  -> 4 adds + 1 add + 1 mul
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep2d_march_poisson8192.json")
-SWEEP_SOURCE = os.path.join(ROOT, "paper_2303_02543_amd", "csrc", "k_sweep.hip")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2303_02543_amd", "csrc", "k_march2d.hip")
 
 
 def parse():
@@ -54,7 +54,24 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device-to-device copies of MIB mebibytes (a "
+                         "known-size kernel for calibrating HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_probe(mib):
+    """Five plain copies of `mib` MiB (torch's copy kernel): each reads and
+    writes exactly mib MiB, the reference for FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_mib": mib, "bytes_read_per_copy": n * 4,
+                      "bytes_written_per_copy": n * 4, "copies": 5}), flush=True)
 
 
 def source_hash(path):
@@ -114,6 +131,9 @@ def main():
         print("bench.py runs on exactly one GPU: the Jacobi library has no multi-GPU path "
               "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.steps < 1 or args.warmup < 0:
         print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
         sys.exit(2)
@@ -184,7 +204,7 @@ def main():
     if flags & jb.JACOBI_FLAG_EXPLICIT_HALO:
         kname = "k_sweep_local<float, true>"
     else:
-        kname = "k_sweep2d_march<float, %d, true>" % d_dom
+        kname = "k_march2d<float, %d, 1>" % d_dom
     traffic = traffic_for(kname, bytes_per_launch)
     hbm_frac = hbm_gbs / HBM_PEAK_GBS
     alu_frac = alu_tops / ALU_PEAK_TOPS

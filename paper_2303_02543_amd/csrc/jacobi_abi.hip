@@ -167,16 +167,39 @@ int check_handle(jacobi_t h) {
     return JACOBI_OK;
 }
 
-// Defaults before any tuning: the fastest schedule measured on MI355X for a
-// 2D FP32 8192^2 grid; explicit halos (depth 1) elsewhere.
+// Tile height that makes one march launch fill the GPU in `rounds` whole
+// rounds of resident waves: strips x tiles ~= rounds x (waves per CU x CUs).
+int balanced_rows(const jacobi_s *h, int depth, int mode, int rounds) {
+    if (h->g.ndim != 2) return 64;
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 64;
+    const int wpc = h->dtype == JACOBI_F32 ? jac::march2d_waves_per_cu<float>(depth, mode)
+                                           : jac::march2d_waves_per_cu<double>(depth, mode);
+    const int64_t strips = h->dtype == JACOBI_F32 ? jac::march2d_strips<float>(h->g, depth)
+                                                  : jac::march2d_strips<double>(h->g, depth);
+    if (wpc <= 0 || strips <= 0) return 64;
+    int64_t tiles = (int64_t)rounds * wpc * cus / strips;
+    if (tiles < 1) tiles = 1;
+    int64_t rows = (h->g.n[1] + tiles - 1) / tiles;
+    if (rows < kMinRows) rows = kMinRows;
+    if (rows > (1 << 20)) rows = 1 << 20;
+    return (int)rows;
+}
+
+// Defaults before any tuning: the fastest depth measured on MI355X for a 2D
+// FP32 8192^2 grid, with a tile height that fills the GPU in one round;
+// explicit halos (depth 1) for 3D.
 int default_depth(const jacobi_s *h) {
     if (h->g.ndim == 3) return 1;
-    return h->dtype == JACOBI_F32 ? 6 : 3;
+    return h->dtype == JACOBI_F32 ? 7 : 4;
 }
 
 int default_rows(const jacobi_s *h) {
-    (void)h;
-    return 64;
+    const int d = h->depth > 0 ? h->depth : default_depth(h);
+    return balanced_rows(h, d, h->has_source ? 1 : 0, 1);
 }
 
 int max_depth(int ndim, int dtype) {
@@ -229,7 +252,7 @@ int do_residual(jacobi_t h, double *out) {
     const void *b = h->has_source ? h->b : nullptr;
     if (h->g.ndim == 2) {
         // one residual-only pass of the march kernel (no stores)
-        const int rows = default_rows(h);
+        const int rows = balanced_rows(h, 1, h->has_source ? 1 : 0, 1);
         const int64_t nw = jac::march2d_work_items<R>(h->g, 1, rows);
         if (nw < 0 || (size_t)nw > h->lay.part_cap) return fail(JACOBI_E_INVAL, "partials overflow");
         int64_t nwork = 0;
@@ -308,7 +331,7 @@ int do_sweep(jacobi_t h, int64_t n, double *res_first) {
 template <typename R>
 int do_adjoint(jacobi_t h, int64_t n) {
     int depth = h->adj_depth > 0 ? h->adj_depth : (h->dtype == JACOBI_F32 ? 4 : 3);
-    const int rows = h->adj_rows > 0 ? h->adj_rows : default_rows(h);
+    const int rows = h->adj_rows > 0 ? h->adj_rows : balanced_rows(h, depth, 2, 1);
     int64_t left = n;
     while (left > 0) {
         const int64_t passes = (left + depth - 1) / depth;
@@ -691,9 +714,19 @@ int jacobi_autotune(jacobi_t h, int64_t n_sweeps, int with_source, int *t_depth,
         if (h->g.ndim == 2) {
             const int *list;
             const int nd = jac::march2d_depths(h->dtype, &list);
-            static const int kRows[] = {16, 32, 48, 64, 96, 128, 192, 256};
-            for (int i = 0; i < nd; ++i)
-                for (int r : kRows) cands.push_back({list[i], r, 0});
+            static const int kRows[] = {16, 32, 64, 96, 128, 192, 256};
+            for (int i = 0; i < nd; ++i) {
+                std::vector<int> rs(kRows, kRows + sizeof(kRows) / sizeof(int));
+                for (int k = 1; k <= 3; ++k) rs.push_back(balanced_rows(h, list[i], src, k));
+                std::vector<int> seen;
+                for (int r : rs) {
+                    bool dup = false;
+                    for (int q : seen) dup = dup || q == r;
+                    if (dup) continue;
+                    seen.push_back(r);
+                    cands.push_back({list[i], r, 0});
+                }
+            }
         }
         const bool saved_src = h->has_source;
         const bool saved_prof = h->profiling;

@@ -455,6 +455,43 @@ int march2d_depths(int dtype, const int **list) {
 }
 
 template <typename R>
+int64_t march2d_work_items(const Geom &g, int depth, int rows);
+
+template <typename R, int T>
+static int m2_waves_per_cu_t(int mode) {
+    int blocks = 0;
+    hipError_t e;
+    if (mode == MODE_ADJOINT)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, MODE_ADJOINT>, 256, 0);
+    else if (mode == MODE_POISSON)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, MODE_POISSON>, 256, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, MODE_LAPLACE>, 256, 0);
+    return e == hipSuccess ? blocks * 4 : 0;
+}
+
+template <typename R>
+int march2d_waves_per_cu(int depth, int mode) {
+    switch (depth) {
+    case 1: return m2_waves_per_cu_t<R, 1>(mode);
+    case 2: return m2_waves_per_cu_t<R, 2>(mode);
+    case 3: return m2_waves_per_cu_t<R, 3>(mode);
+    case 4: return m2_waves_per_cu_t<R, 4>(mode);
+    case 5: return m2_waves_per_cu_t<R, 5>(mode);
+    case 6: return m2_waves_per_cu_t<R, 6>(mode);
+    case 7: return m2_waves_per_cu_t<R, 7>(mode);
+    case 8: return m2_waves_per_cu_t<R, 8>(mode);
+    default: return 0;
+    }
+}
+
+template <typename R>
+int64_t march2d_strips(const Geom &g, int depth) {
+    const int64_t nw = march2d_work_items<R>(g, depth, g.n[1]);  // one tile per strip
+    return nw;
+}
+
+template <typename R>
 int64_t march2d_work_items(const Geom &g, int depth, int rows) {
     switch (depth) {
     case 1: return m2_nwork<R, 1>(g, rows, nullptr);
@@ -501,5 +538,9 @@ hipError_t launch_sweep2d_march<double>(const Geom &g, const void *uin, void *uo
 
 template int64_t march2d_work_items<float>(const Geom &, int, int);
 template int64_t march2d_work_items<double>(const Geom &, int, int);
+template int march2d_waves_per_cu<float>(int, int);
+template int march2d_waves_per_cu<double>(int, int);
+template int64_t march2d_strips<float>(const Geom &, int);
+template int64_t march2d_strips<double>(const Geom &, int);
 
 }  // namespace jac

@@ -42,6 +42,13 @@ hipError_t launch_sweep2d_march(const Geom &g, const void *uin, void *uout, cons
 // Work items (waves) of one march launch; -1 for an unknown depth.
 template <typename R>
 int64_t march2d_work_items(const Geom &g, int depth, int rows);
+// Resident waves per CU of the depth-`depth` march kernel in `mode`
+// (0 Laplace, 1 Poisson, 2 adjoint); 0 if unknown.
+template <typename R>
+int march2d_waves_per_cu(int depth, int mode);
+// Strips (work items per tile row) of the depth-`depth` march kernel.
+template <typename R>
+int64_t march2d_strips(const Geom &g, int depth);
 // Depths compiled for the 2D march kernel, ascending; returns the count.
 int march2d_depths(int dtype, const int **list);
 
