@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched and adjoint measurements")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device-to-device copies of MIB mebibytes (a "
                          "known-size kernel for calibrating HBM byte counters) and exit")
@@ -72,6 +74,103 @@ def copy_probe(mib):
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_mib": mib, "bytes_read_per_copy": n * 4,
                       "bytes_written_per_copy": n * 4, "copies": 5}), flush=True)
+
+
+def bench_batched(plain_glups):
+    """64 independent 2D Poisson grids, sides uniform on [257, 4097]
+    (default_rng(4)), per-grid 16-Gaussian sources (default_rng(4000+g)), FP32
+    with FP64 residual, stop at relative residual 1e-6 or 5000 sweeps, residual
+    every 50; one launch per pass over all active grids, check intervals
+    replayed as hipGraphs, autotuned depth and tile height."""
+    import numpy as np
+    import torch
+    import paper_2303_02543_amd as jb
+    import synthetic
+    dev = torch.device("cuda:0")
+    sizes = [int(n) for n in synthetic.batched_sizes()]
+    srcs = [torch.from_numpy(synthetic.batched_source(n, g).astype(np.float32)).to(dev)
+            for g, n in enumerate(sizes)]
+    zeros = [torch.zeros((n + 2, n + 2), dtype=torch.float32, device=dev) for n in sizes]
+    B = jb.Batch([(n, n) for n in sizes], torch.float32, block=512, device=dev)
+    try:
+        depth, rows = B.autotune(50)
+        B.set_tuning(depth, rows, True)
+
+        def solve():
+            for g, n in enumerate(sizes):
+                B.set_grid(g, zeros[g], srcs[g], synthetic.spacing2(n))
+            return B.solve(1e-6, 5000, 50)
+
+        solve()  # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sw, rl, st = solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        B.close()
+    updates = float(sum(n * n * k for n, k in zip(sizes, sw)))
+    glups = updates / dt / 1e9
+    counts = {}
+    for v in st:
+        counts[jb.STATUS_NAMES[v]] = counts.get(jb.STATUS_NAMES[v], 0) + 1
+    return {
+        "workload": "64 independent 2D 5-point Poisson grids, sides U{257..4097}, FP32, FP64 "
+                    "residual every 50, stop at rel 1e-6 or 5000 sweeps",
+        "grids": len(sizes), "sum_n2": int(sum(n * n for n in sizes)),
+        "cell_updates": updates, "seconds": round(dt, 4), "glups": round(glups, 3),
+        "ratio_vs_plain": round(glups / plain_glups, 4), "t_depth": depth, "rows": rows,
+        "graph": True, "status_counts": counts,
+        "rel_min": min(rl), "rel_max": max(rl),
+    }
+
+
+def bench_adjoint(plain_glups):
+    """Adjoint: L = 1/2 ||u_K - t||^2 on 4096^2 FP32 2D Poisson, K = 500,
+    checkpoint interval C = 50, gradients w.r.t. the source and the boundary
+    values through JacobiK (forward sweeps, then the hand-written adjoint
+    passes with FP64 accumulation)."""
+    import numpy as np
+    import torch
+    import paper_2303_02543_amd as jb
+    import synthetic
+    from paper_2303_02543_amd.autograd import JacobiK
+    dev = torch.device("cuda:0")
+    n, K, C = 4096, 500, 50
+    U0, f, t = synthetic.adjoint_c5(n)
+    h2 = synthetic.spacing2(n)
+    U0d = torch.from_numpy(U0.astype(np.float32)).to(dev)
+    fd = torch.from_numpy(f.astype(np.float32)).to(dev)
+    td = torch.from_numpy(t.astype(np.float32)).to(dev)
+    s = jb.Solver((n, n), (8, 8), torch.float32, device=dev)
+    try:
+        def run():
+            fT = fd.clone().requires_grad_(True)
+            UT = U0d.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            uK = JacobiK.apply(fT, UT, s, K, h2, C)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            loss = 0.5 * ((uK[1:-1, 1:-1] - td) ** 2).sum()
+            loss.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            return t1 - t0, t2 - t1, float(loss)
+        run()
+        fwd, bwd, L = run()
+    finally:
+        s.close()
+    cells = float(n) * n
+    return {
+        "workload": "adjoint of 1/2||u_K - t||^2, 4096^2 FP32 2D Poisson, K=500, C=50",
+        "forward_ms": round(fwd * 1e3, 3), "backward_ms": round(bwd * 1e3, 3),
+        "fwd_plus_bwd_over_fwd": round((fwd + bwd) / fwd, 4),
+        "forward_glups": round(cells * K / fwd / 1e9, 3),
+        "adjoint_glups": round(cells * K / bwd / 1e9, 3),
+        "adjoint_ratio_vs_plain": round(cells * K / bwd / 1e9 / plain_glups, 4),
+        "loss": L,
+    }
 
 
 def source_hash(path):
@@ -254,6 +353,9 @@ def main():
         "residual_ratio": float(res[-1].item() / res[0].item()),
     }
     s.close()
+    if not args.no_forms:
+        out["batched"] = bench_batched(glups)
+        out["adjoint"] = bench_adjoint(glups)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(U0_np, f32, h2, args.cpu_seconds)
     else:

@@ -151,6 +151,71 @@ int jacobi_get_tuning(jacobi_t h, int *t_depth, int *rows, int *flags);
 /* Largest temporal depth this build supports for the handle's ndim/dtype. */
 int jacobi_max_depth(int ndim, int dtype);
 
+/* --------------------------------------------------------------- batched */
+/*
+ * Many independent 2D Poisson grids of uneven sizes solved together: every
+ * pass is one launch over the tiles of all grids that are still active, the
+ * FP64 residual of each grid is folded into the first pass of each check
+ * interval, and the relative-residual stop test runs on the GPU, so one
+ * interval (its passes, counters and tests) is captured once as a hipGraph
+ * and replayed.  Stop rule per grid (a reading; the paper runs a fixed
+ * iteration count): residuals are checked on the states after 0, R, 2R, ...
+ * sweeps and after max_sweeps; a grid stops, converged, at the first checked
+ * k > 0 with res_k / res_0 <= rel_tol, converged at 0 sweeps if res_0 == 0,
+ * diverged if a residual is not finite, otherwise at max_sweeps.  A stopped
+ * grid keeps the state it was checked on.
+ */
+typedef struct jacobi_batch_s *jacobi_batch_t; /* opaque handle */
+
+enum jacobi_batch_status {
+    JACOBI_RUNNING = 0,
+    JACOBI_CONVERGED = 1,
+    JACOBI_MAX_SWEEPS = 2,
+    JACOBI_DIVERGED = 3
+};
+
+/* Workspace for `count` grids; grids: count pairs (n_x, n_y) of interior
+ * sizes (host array); block: target block side (>= 8; blocks per axis =
+ * ceil(n / block), reduced if the last block would be empty).  dtype as for
+ * jacobi_create. */
+int jacobi_batch_workspace_bytes(int count, const int64_t *grids, int64_t block, int dtype,
+                                 size_t *bytes);
+
+/* Create a batch over a caller-owned device workspace (256-byte aligned).
+ * stream: hipStream_t; hipGraph capture needs a non-NULL stream (with NULL
+ * the intervals are launched one kernel at a time). */
+int jacobi_batch_create(int count, const int64_t *grids, int64_t block, int dtype,
+                        void *workspace, size_t workspace_bytes, void *stream,
+                        jacobi_batch_t *out);
+
+/* Wait for the stream, release graphs and host memory.  NULL is a no-op. */
+int jacobi_batch_destroy(jacobi_batch_t b);
+
+/* Set grid i: u full state (ring + interior) and f interior source, both
+ * device arrays of the batch dtype in the single-grid layout; b = fl(h2 f).
+ * Every grid must be set before a solve. */
+int jacobi_batch_set_grid(jacobi_batch_t b, int i, const void *u, const void *f, double h2);
+
+/* Gather grid i's final state (the state its stop test was taken on) into u. */
+int jacobi_batch_get_grid(jacobi_batch_t b, int i, void *u);
+
+/* Schedule: temporal depth (0 = default), tile rows (0 = default, else >= 8),
+ * use_graph (replay captured check intervals). */
+int jacobi_batch_set_tuning(jacobi_batch_t b, int t_depth, int rows, int use_graph);
+int jacobi_batch_get_tuning(jacobi_batch_t b, int *t_depth, int *rows, int *use_graph);
+
+/* Time candidate depths and tile heights on one check interval of
+ * check_every sweeps and keep the fastest (all are bit-identical).  Uses the
+ * grids' buffers as scratch: every grid must be set again afterwards.
+ * Synchronises the stream.  Outputs may be NULL. */
+int jacobi_batch_autotune(jacobi_batch_t b, int64_t check_every, int *t_depth, int *rows);
+
+/* Solve every grid with the stop rule above.  Host outputs (count entries
+ * each, may be NULL): sweeps of the final state, its relative residual, and
+ * the jacobi_batch_status.  Synchronises the stream. */
+int jacobi_batch_solve(jacobi_batch_t b, double rel_tol, int64_t max_sweeps, int64_t check_every,
+                       int64_t *sweeps, double *rel, int *status);
+
 /* --------------------------------------------------------------- adjoint */
 /*
  * Reverse-mode derivative through K 2D sweeps (not in the paper; the

@@ -71,6 +71,8 @@ int orc_adjoint2d_f64(int64_t nx, int64_t ny, int64_t K, const double *lamK,
     memset(Gring, 0, cnt * sizeof(double));
     const double w = 0.25;
     for (int64_t k = K; k >= 1; --k) {
+        /* cells are independent; each cell still adds its terms in k order */
+#pragma omp parallel for schedule(static)
         for (int64_t j = 1; j <= ny; ++j)
             for (int64_t i = 1; i <= nx; ++i) Gb[(j - 1) * nx + (i - 1)] += w * lam[j * ld + i];
         for (int64_t i = 1; i <= nx; ++i) {

@@ -20,6 +20,12 @@ JACOBI_F32 = 0
 JACOBI_F64 = 1
 JACOBI_FLAG_EXPLICIT_HALO = 1
 
+JACOBI_RUNNING = 0
+JACOBI_CONVERGED = 1
+JACOBI_MAX_SWEEPS = 2
+JACOBI_DIVERGED = 3
+STATUS_NAMES = {0: "running", 1: "converged", 2: "max_sweeps", 3: "diverged"}
+
 JACOBI_OK = 0
 JACOBI_E_INVAL = -1
 JACOBI_E_NOMEM = -2
@@ -54,6 +60,15 @@ _SIGNATURES = {
     "jacobi_set_tuning": [_P, _I, _I, _I],
     "jacobi_get_tuning": [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)],
     "jacobi_max_depth": [_I, _I],
+    "jacobi_batch_workspace_bytes": [_I, _PI64, _I64, _I, ctypes.POINTER(_SZ)],
+    "jacobi_batch_create": [_I, _PI64, _I64, _I, _P, _SZ, _P, ctypes.POINTER(_P)],
+    "jacobi_batch_destroy": [_P],
+    "jacobi_batch_set_grid": [_P, _I, _P, _P, _D],
+    "jacobi_batch_get_grid": [_P, _I, _P],
+    "jacobi_batch_set_tuning": [_P, _I, _I, _I],
+    "jacobi_batch_get_tuning": [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)],
+    "jacobi_batch_autotune": [_P, _I64, ctypes.POINTER(_I), ctypes.POINTER(_I)],
+    "jacobi_batch_solve": [_P, _D, _I64, _I64, _PI64, ctypes.POINTER(_D), ctypes.POINTER(_I)],
     "jacobi_adjoint_begin": [_P, _P, _P],
     "jacobi_adjoint_sweep": [_P, _I64],
     "jacobi_adjoint_end": [_P, _D, _P, _P],
@@ -205,6 +220,60 @@ def jacobi_max_depth(ndim, dtype):
     if v < 0:
         _check(v)
     return v
+
+
+def jacobi_batch_workspace_bytes(grids, block, dtype):
+    flat = [int(v) for g in grids for v in g]
+    out = _SZ(0)
+    _check(lib().jacobi_batch_workspace_bytes(len(grids), _arr64(flat), int(block), int(dtype),
+                                              ctypes.byref(out)))
+    return out.value
+
+
+def jacobi_batch_create(grids, block, dtype, workspace_ptr, workspace_bytes, stream_ptr):
+    flat = [int(v) for g in grids for v in g]
+    h = _P()
+    _check(lib().jacobi_batch_create(len(grids), _arr64(flat), int(block), int(dtype),
+                                     workspace_ptr, int(workspace_bytes), stream_ptr,
+                                     ctypes.byref(h)))
+    return h
+
+
+def jacobi_batch_destroy(b):
+    _check(lib().jacobi_batch_destroy(b))
+
+
+def jacobi_batch_set_grid(b, i, u_ptr, f_ptr, h2):
+    _check(lib().jacobi_batch_set_grid(b, int(i), u_ptr, f_ptr, float(h2)))
+
+
+def jacobi_batch_get_grid(b, i, u_ptr):
+    _check(lib().jacobi_batch_get_grid(b, int(i), u_ptr))
+
+
+def jacobi_batch_set_tuning(b, t_depth=0, rows=0, use_graph=1):
+    _check(lib().jacobi_batch_set_tuning(b, int(t_depth), int(rows), int(use_graph)))
+
+
+def jacobi_batch_get_tuning(b):
+    d, r, g = _I(), _I(), _I()
+    _check(lib().jacobi_batch_get_tuning(b, ctypes.byref(d), ctypes.byref(r), ctypes.byref(g)))
+    return d.value, r.value, g.value
+
+
+def jacobi_batch_autotune(b, check_every):
+    d, r = _I(), _I()
+    _check(lib().jacobi_batch_autotune(b, int(check_every), ctypes.byref(d), ctypes.byref(r)))
+    return d.value, r.value
+
+
+def jacobi_batch_solve(b, count, rel_tol, max_sweeps, check_every):
+    sw = (ctypes.c_int64 * count)()
+    rl = (ctypes.c_double * count)()
+    st = (ctypes.c_int * count)()
+    _check(lib().jacobi_batch_solve(b, float(rel_tol), int(max_sweeps), int(check_every), sw, rl,
+                                    st))
+    return list(sw), list(rl), list(st)
 
 
 def jacobi_adjoint_begin(h, lam_ptr, grad_b_ptr):
@@ -394,6 +463,91 @@ class Solver:
     def close(self):
         if getattr(self, "h", None) is not None:
             jacobi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent 2D Poisson grids of uneven sizes solved together.
+
+    grids: list of (n_x, n_y) interior sizes; dtype torch.float32/float64;
+    block: target block side of each grid's decomposition.  The batch runs on
+    its own (default-priority) stream so that check intervals can be captured
+    as hipGraphs; set_grid / get_grid / solve order it against the caller's
+    current stream."""
+
+    def __init__(self, grids, dtype, block=512, device="cuda"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the Jacobi library has no CPU path")
+        self.grids = [(int(a), int(b)) for a, b in grids]
+        self.count = len(self.grids)
+        self.torch_dtype = dtype
+        self.dtype = dtype_code(dtype)
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        nbytes = jacobi_batch_workspace_bytes(self.grids, block, self.dtype)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._keep = []
+        self.h = jacobi_batch_create(self.grids, block, self.dtype, _ptr(self.workspace), nbytes,
+                                     ctypes.c_void_p(self.stream.cuda_stream))
+
+    def _enter(self):
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        import torch
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def set_grid(self, i, U, f, h2):
+        nx, ny = self.grids[i]
+        for t, shape, name in ((U, (ny + 2, nx + 2), "state"), (f, (ny, nx), "source")):
+            if t.dtype != self.torch_dtype or tuple(t.shape) != shape or not t.is_contiguous() \
+                    or t.device != self.device:
+                raise ValueError("%s of grid %d must be a contiguous %s tensor of shape %s on %s"
+                                 % (name, i, self.torch_dtype, shape, self.device))
+        self._enter()
+        self._keep.extend([U, f])
+        jacobi_batch_set_grid(self.h, i, _ptr(U), _ptr(f), h2)
+
+    def get_grid(self, i):
+        import torch
+        nx, ny = self.grids[i]
+        out = torch.empty((ny + 2, nx + 2), dtype=self.torch_dtype, device=self.device)
+        self._enter()
+        jacobi_batch_get_grid(self.h, i, _ptr(out))
+        self._leave()
+        return out
+
+    def set_tuning(self, t_depth=0, rows=0, use_graph=True):
+        jacobi_batch_set_tuning(self.h, t_depth, rows, 1 if use_graph else 0)
+
+    def get_tuning(self):
+        return jacobi_batch_get_tuning(self.h)
+
+    def autotune(self, check_every):
+        self._enter()
+        out = jacobi_batch_autotune(self.h, check_every)
+        self._keep = []
+        return out
+
+    def solve(self, rel_tol, max_sweeps, check_every):
+        """Returns (sweeps, rel, status) lists, one entry per grid."""
+        self._enter()
+        out = jacobi_batch_solve(self.h, self.count, rel_tol, max_sweeps, check_every)
+        self._keep = []
+        self._leave()
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            jacobi_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

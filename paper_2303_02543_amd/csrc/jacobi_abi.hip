@@ -793,3 +793,499 @@ const char *jacobi_strerror(int status) {
 const char *jacobi_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
+
+// ====================================================================== batch
+namespace {
+
+constexpr int kMaxDepth = 8;
+
+struct BatchLayout {
+    std::vector<Geom> geoms;
+    std::vector<Layout> lays;
+    std::vector<size_t> base;  // workspace offset of each grid's buffers
+    size_t off_grids, off_prefix, off_state, off_part, part_cap, bytes;
+};
+
+// Pick blocks per axis so that blocks have about `block` interior nodes per side.
+int batch_plan(int count, const int64_t *grids, int64_t block, int dtype, BatchLayout *bl) {
+    if (count < 1 || count > (1 << 20)) return fail(JACOBI_E_INVAL, "count must be in [1, 2^20]");
+    if (!grids) return fail(JACOBI_E_INVAL, "grids must not be NULL");
+    if (block < 8 || block > (1 << 30)) return fail(JACOBI_E_INVAL, "block must be in [8, 2^30]");
+    bl->geoms.resize(count);
+    bl->lays.resize(count);
+    bl->base.resize(count);
+    size_t off = 0, cap = 0, t;
+    for (int i = 0; i < count; ++i) {
+        const int64_t g2[2] = {grids[2 * i], grids[2 * i + 1]};
+        if (g2[0] < 1 || g2[1] < 1 || g2[0] > (1 << 30) || g2[1] > (1 << 30))
+            return fail(JACOBI_E_INVAL, "grid %d has a side out of [1, 2^30]", i);
+        int64_t b2[2];
+        int rc = JACOBI_E_INVAL;
+        for (int a = 0; a < 2; ++a) b2[a] = (g2[a] + block - 1) / block;
+        // the x extent is rounded up to 32 bytes of elements, which can leave
+        // the last block empty: use fewer blocks until the split is valid
+        for (int tries = 0; tries < 64 && rc != JACOBI_OK; ++tries) {
+            rc = plan(2, g2, b2, dtype, &bl->geoms[i], &bl->lays[i]);
+            if (rc != JACOBI_OK) {
+                if (b2[0] > 1) --b2[0];
+                else if (b2[1] > 1) --b2[1];
+                else break;
+            }
+        }
+        if (rc != JACOBI_OK) return rc;
+        bl->base[i] = off;
+        // a grid needs its two state buffers and its source (not the
+        // single-grid partials/scratch area)
+        if (!add_ok(off, bl->lays[i].off_part, &t)) return fail(JACOBI_E_INVAL, "size overflow");
+        off = round_up(t, kAlign);
+        cap += ((size_t)g2[0] / 32 + 2) * ((size_t)g2[1] / kMinRows + 2);
+    }
+    bl->off_grids = off;
+    off = round_up(off + sizeof(jac::BatchGrid) * count, kAlign);
+    bl->off_prefix = off;
+    off = round_up(off + sizeof(int) * (size_t)(count + 1) * (kMaxDepth + 1), kAlign);
+    bl->off_state = off;
+    // active, status, final_buf (int); sweeps (int64); rel, res0, res (double); 2 counters
+    off = round_up(off + (size_t)count * (3 * sizeof(int) + sizeof(long long) + 3 * sizeof(double)) +
+                       64,
+                   kAlign);
+    bl->off_part = off;
+    bl->part_cap = cap;
+    if (!add_ok(off, sizeof(double) * cap, &t)) return fail(JACOBI_E_INVAL, "size overflow");
+    bl->bytes = round_up(t, kAlign);
+    return JACOBI_OK;
+}
+
+}  // namespace
+
+struct jacobi_batch_s {
+    int count, dtype;
+    BatchLayout bl;
+    char *ws;
+    hipStream_t stream;
+    jac::BatchGrid *d_grids;
+    int *d_prefix;  // (kMaxDepth + 1) arrays of count + 1 work offsets, indexed by depth
+    jac::BatchState st;
+    double *partials;
+    std::vector<jac::BatchGrid> h_grids;
+    std::vector<int> h_prefix;
+    std::vector<int> h_final_buf;
+    std::vector<char> grid_set;
+    int depth, rows, use_graph;
+    int table_rows;  // tile height the uploaded tables were built for (0: none)
+    int *h_active;   // pinned host copy of the activity flags
+    // captured interval
+    hipGraphExec_t graph;
+    int64_t graph_R;
+    int graph_depth, graph_rows;
+    double graph_tol;
+};
+
+namespace {
+
+int batch_check(jacobi_batch_t b) {
+    if (!b) return fail(JACOBI_E_INVAL, "batch handle is NULL");
+    return JACOBI_OK;
+}
+
+void batch_drop_graph(jacobi_batch_t b) {
+    if (b->graph) hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    b->graph_R = 0;
+}
+
+int batch_rows(const jacobi_batch_t b) { return b->rows > 0 ? b->rows : 64; }
+int batch_depth(const jacobi_batch_t b) {
+    return b->depth > 0 ? b->depth : (b->dtype == JACOBI_F32 ? 7 : 4);
+}
+
+// Work tables for the current tile height: per grid its tiles per strip, and
+// per depth the prefix sums of work items.  Uploaded when the height changes.
+template <typename R>
+int batch_tables(jacobi_batch_t b) {
+    const int rows = batch_rows(b);
+    if (b->table_rows == rows) return JACOBI_OK;
+    const int n = b->count;
+    b->h_prefix.assign((size_t)(kMaxDepth + 1) * (n + 1), 0);
+    for (int d = 1; d <= kMaxDepth; ++d) {
+        int *pre = &b->h_prefix[(size_t)d * (n + 1)];
+        int64_t acc = 0;
+        for (int i = 0; i < n; ++i) {
+            int nseg = 0;
+            pre[i] = (int)acc;
+            const int64_t w = jac::march2d_batch_work<R>(b->bl.geoms[i], d, rows, &nseg);
+            if (w < 0) { acc = -1; break; }
+            b->h_grids[i].nseg = nseg;
+            acc += w;
+            if (acc > 0x3fffffff) return fail(JACOBI_E_INVAL, "batch work exceeds 2^30 items");
+        }
+        if (acc >= 0) {
+            pre[n] = (int)acc;
+            if ((size_t)acc > b->bl.part_cap) return fail(JACOBI_E_INVAL, "partials overflow");
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(b->d_grids, b->h_grids.data(), sizeof(jac::BatchGrid) * n,
+                           hipMemcpyHostToDevice, b->stream),
+            "batch table upload");
+    HIP_TRY(hipMemcpyAsync(b->d_prefix, b->h_prefix.data(), sizeof(int) * b->h_prefix.size(),
+                           hipMemcpyHostToDevice, b->stream),
+            "batch table upload");
+    HIP_TRY(hipStreamSynchronize(b->stream), "stream synchronize");
+    b->table_rows = rows;
+    batch_drop_graph(b);
+    return JACOBI_OK;
+}
+
+// Depths of the passes of an interval of n sweeps (even split, at most `depth`).
+std::vector<int> batch_passes(int dtype, int depth, int64_t n) {
+    std::vector<int> out;
+    int64_t left = n;
+    while (left > 0) {
+        const int64_t passes = (left + depth - 1) / depth;
+        const int t = pick_depth(dtype, (int)((left + passes - 1) / passes));
+        out.push_back(t);
+        left -= t;
+    }
+    return out;
+}
+
+// One check interval: passes of n sweeps in total, the first also summing the
+// residual of the interval's starting state, which the stop test then checks.
+// check = false (autotuning): no residual and no stop test, so scratch
+// contents cannot deactivate grids and every candidate does the full work.
+template <typename R>
+int batch_interval(jacobi_batch_t b, int64_t n, double tol, bool check = true) {
+    const std::vector<int> ds = batch_passes(b->dtype, batch_depth(b), n);
+    const int rows = batch_rows(b);
+    const int cnt = b->count;
+    for (size_t p = 0; p < ds.size(); ++p) {
+        const int t = ds[p];
+        const int *pre = b->d_prefix + (size_t)t * (cnt + 1);
+        const int nwork = b->h_prefix[(size_t)t * (cnt + 1) + cnt];
+        HIP_TRY(jac::launch_march2d_batch<R>(b->d_grids, pre, cnt, b->st.active, b->st.pass_count,
+                                             (p == 0 && check) ? b->partials : nullptr, true, t,
+                                             rows, nwork, b->stream),
+                "batch pass launch");
+        if (p == 0 && check)
+            HIP_TRY(jac::launch_batch_check(pre, b->partials, cnt, b->st, tol, false, b->stream),
+                    "batch check launch");
+        HIP_TRY(jac::launch_batch_advance(b->st, t, b->stream), "batch advance launch");
+    }
+    return JACOBI_OK;
+}
+
+// Residual of the current states of the active grids and the final test.
+template <typename R>
+int batch_final(jacobi_batch_t b, double tol) {
+    const int cnt = b->count;
+    const int *pre = b->d_prefix + (size_t)1 * (cnt + 1);
+    const int nwork = b->h_prefix[(size_t)1 * (cnt + 1) + cnt];
+    HIP_TRY(jac::launch_march2d_batch<R>(b->d_grids, pre, cnt, b->st.active, b->st.pass_count,
+                                         b->partials, false, 1, batch_rows(b), nwork, b->stream),
+            "batch residual launch");
+    HIP_TRY(jac::launch_batch_check(pre, b->partials, cnt, b->st, tol, true, b->stream),
+            "batch check launch");
+    return JACOBI_OK;
+}
+
+template <typename R>
+int batch_capture(jacobi_batch_t b, int64_t n, double tol) {
+    if (b->graph && b->graph_R == n && b->graph_depth == batch_depth(b) &&
+        b->graph_rows == batch_rows(b) && b->graph_tol == tol)
+        return JACOBI_OK;
+    batch_drop_graph(b);
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    const int rc = batch_interval<R>(b, n, tol);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    if (rc) {
+        if (graph) hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e2 != hipSuccess) return hip_fail(e2, "graph instantiate");
+    b->graph = exec;
+    b->graph_R = n;
+    b->graph_depth = batch_depth(b);
+    b->graph_rows = batch_rows(b);
+    b->graph_tol = tol;
+    return JACOBI_OK;
+}
+
+template <typename R>
+int batch_solve(jacobi_batch_t b, double tol, int64_t max_sweeps, int64_t R_, int64_t *sweeps,
+                double *rel, int *status) {
+    int rc = batch_tables<R>(b);
+    if (rc) return rc;
+    const int cnt = b->count;
+    HIP_TRY(jac::launch_batch_init(cnt, b->st, b->stream), "batch init launch");
+    const int64_t full = max_sweeps / R_, rem = max_sweeps % R_;
+    const bool graphs = b->use_graph && b->stream != nullptr && full > 0;
+    if (graphs) {
+        rc = batch_capture<R>(b, R_, tol);
+        if (rc) return rc;
+    }
+    for (int64_t i = 0; i < full; ++i) {
+        if (graphs)
+            HIP_TRY(hipGraphLaunch(b->graph, b->stream), "graph launch");
+        else if ((rc = batch_interval<R>(b, R_, tol)))
+            return rc;
+        if ((i + 1) % 4 == 0 && i + 1 < full) {
+            // stop early once every grid has stopped
+            HIP_TRY(hipMemcpyAsync(b->h_active, b->st.active, sizeof(int) * cnt,
+                                   hipMemcpyDeviceToHost, b->stream),
+                    "activity copy");
+            HIP_TRY(hipStreamSynchronize(b->stream), "stream synchronize");
+            int any = 0;
+            for (int g = 0; g < cnt; ++g) any |= b->h_active[g];
+            if (!any) break;
+        }
+    }
+    if (rem > 0 && (rc = batch_interval<R>(b, rem, tol))) return rc;
+    if ((rc = batch_final<R>(b, tol))) return rc;
+    std::vector<long long> sw(cnt);
+    std::vector<double> rl(cnt);
+    std::vector<int> stt(cnt);
+    HIP_TRY(hipMemcpyAsync(sw.data(), b->st.sweeps, sizeof(long long) * cnt, hipMemcpyDeviceToHost,
+                           b->stream),
+            "result copy");
+    HIP_TRY(hipMemcpyAsync(rl.data(), b->st.rel, sizeof(double) * cnt, hipMemcpyDeviceToHost,
+                           b->stream),
+            "result copy");
+    HIP_TRY(hipMemcpyAsync(stt.data(), b->st.status, sizeof(int) * cnt, hipMemcpyDeviceToHost,
+                           b->stream),
+            "result copy");
+    HIP_TRY(hipMemcpyAsync(b->h_final_buf.data(), b->st.final_buf, sizeof(int) * cnt,
+                           hipMemcpyDeviceToHost, b->stream),
+            "result copy");
+    HIP_TRY(hipStreamSynchronize(b->stream), "stream synchronize");
+    for (int g = 0; g < cnt; ++g) {
+        if (sweeps) sweeps[g] = sw[g];
+        if (rel) rel[g] = rl[g];
+        if (status) status[g] = stt[g];
+    }
+    return JACOBI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int jacobi_batch_workspace_bytes(int count, const int64_t *grids, int64_t block, int dtype,
+                                 size_t *bytes) {
+    if (!bytes) return fail(JACOBI_E_INVAL, "bytes must not be NULL");
+    BatchLayout bl;
+    const int rc = batch_plan(count, grids, block, dtype, &bl);
+    if (rc) return rc;
+    *bytes = bl.bytes;
+    return JACOBI_OK;
+}
+
+int jacobi_batch_create(int count, const int64_t *grids, int64_t block, int dtype,
+                        void *workspace, size_t workspace_bytes, void *stream,
+                        jacobi_batch_t *out) {
+    if (!out) return fail(JACOBI_E_INVAL, "out must not be NULL");
+    *out = nullptr;
+    BatchLayout bl;
+    int rc = batch_plan(count, grids, block, dtype, &bl);
+    if (rc) return rc;
+    if (!workspace) return fail(JACOBI_E_INVAL, "workspace must not be NULL");
+    if ((uintptr_t)workspace % kAlign)
+        return fail(JACOBI_E_INVAL, "workspace must be %zu-byte aligned", kAlign);
+    if (workspace_bytes < bl.bytes)
+        return fail(JACOBI_E_NOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, bl.bytes);
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, workspace);
+    if (e != hipSuccess) return hip_fail(e, "workspace pointer query");
+    if (attr.type != hipMemoryTypeDevice) return fail(JACOBI_E_INVAL, "workspace is not device memory");
+    jacobi_batch_s *b = new (std::nothrow) jacobi_batch_s();
+    if (!b) return fail(JACOBI_E_NOMEM, "host allocation failed");
+    b->count = count;
+    b->dtype = dtype;
+    b->bl = bl;
+    b->ws = (char *)workspace;
+    b->stream = (hipStream_t)stream;
+    b->d_grids = (jac::BatchGrid *)(b->ws + bl.off_grids);
+    b->d_prefix = (int *)(b->ws + bl.off_prefix);
+    char *sp = b->ws + bl.off_state;
+    b->st.active = (int *)sp;
+    b->st.status = b->st.active + count;
+    b->st.final_buf = b->st.status + count;
+    sp = (char *)round_up((uintptr_t)(b->st.final_buf + count), 8);
+    b->st.sweeps = (long long *)sp;
+    b->st.rel = (double *)(b->st.sweeps + count);
+    b->st.res0 = b->st.rel + count;
+    b->st.res = b->st.res0 + count;
+    b->st.k_now = (long long *)(b->st.res + count);
+    b->st.pass_count = (int *)(b->st.k_now + 1);
+    b->partials = (double *)(b->ws + bl.off_part);
+    b->h_grids.resize(count);
+    for (int i = 0; i < count; ++i) {
+        jac::BatchGrid &g = b->h_grids[i];
+        std::memset(&g, 0, sizeof g);
+        g.g = bl.geoms[i];
+        g.u[0] = b->ws + bl.base[i] + bl.lays[i].off_u0;
+        g.u[1] = b->ws + bl.base[i] + bl.lays[i].off_u1;
+        g.b = b->ws + bl.base[i] + bl.lays[i].off_b;
+    }
+    b->h_final_buf.assign(count, 0);
+    b->grid_set.assign(count, 0);
+    b->depth = 0;
+    b->rows = 0;
+    b->use_graph = 1;
+    b->table_rows = 0;
+    b->graph = nullptr;
+    b->graph_R = 0;
+    if (hipHostMalloc((void **)&b->h_active, sizeof(int) * count, hipHostMallocDefault) != hipSuccess) {
+        delete b;
+        return fail(JACOBI_E_NOMEM, "pinned host allocation failed");
+    }
+    *out = b;
+    return JACOBI_OK;
+}
+
+int jacobi_batch_destroy(jacobi_batch_t b) {
+    if (!b) return JACOBI_OK;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    hipHostFree(b->h_active);
+    delete b;
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize in destroy");
+    return JACOBI_OK;
+}
+
+int jacobi_batch_set_grid(jacobi_batch_t b, int i, const void *u, const void *f, double h2) {
+    int rc = batch_check(b);
+    if (rc) return rc;
+    if (i < 0 || i >= b->count) return fail(JACOBI_E_INVAL, "grid index %d out of range", i);
+    if (!u || !f) return fail(JACOBI_E_INVAL, "u and f must not be NULL");
+    if (!(h2 > 0.0) || !std::isfinite(h2))
+        return fail(JACOBI_E_INVAL, "h2 must be positive and finite (got %g)", h2);
+    const jac::BatchGrid &g = b->h_grids[i];
+    if (b->dtype == JACOBI_F32) {
+        HIP_TRY(jac::launch_scatter<float>(g.g, u, g.u[0], g.u[1], false, b->stream), "scatter launch");
+        HIP_TRY(jac::launch_halo_exchange<float>(g.g, g.u[0], b->stream), "halo launch");
+        HIP_TRY(jac::launch_halo_exchange<float>(g.g, g.u[1], b->stream), "halo launch");
+        HIP_TRY(jac::launch_scale_source<float>(g.g, f, (void *)g.b, h2, b->stream), "source launch");
+    } else {
+        HIP_TRY(jac::launch_scatter<double>(g.g, u, g.u[0], g.u[1], false, b->stream), "scatter launch");
+        HIP_TRY(jac::launch_halo_exchange<double>(g.g, g.u[0], b->stream), "halo launch");
+        HIP_TRY(jac::launch_halo_exchange<double>(g.g, g.u[1], b->stream), "halo launch");
+        HIP_TRY(jac::launch_scale_source<double>(g.g, f, (void *)g.b, h2, b->stream), "source launch");
+    }
+    b->h_final_buf[i] = 0;
+    b->grid_set[i] = 1;
+    return JACOBI_OK;
+}
+
+int jacobi_batch_get_grid(jacobi_batch_t b, int i, void *u) {
+    int rc = batch_check(b);
+    if (rc) return rc;
+    if (i < 0 || i >= b->count) return fail(JACOBI_E_INVAL, "grid index %d out of range", i);
+    if (!u) return fail(JACOBI_E_INVAL, "u must not be NULL");
+    if (!b->grid_set[i]) return fail(JACOBI_E_STATE, "grid %d has no state", i);
+    const jac::BatchGrid &g = b->h_grids[i];
+    const void *src = g.u[b->h_final_buf[i] & 1];
+    if (b->dtype == JACOBI_F32)
+        HIP_TRY(jac::launch_gather<float>(g.g, src, u, b->stream), "gather launch");
+    else
+        HIP_TRY(jac::launch_gather<double>(g.g, src, u, b->stream), "gather launch");
+    return JACOBI_OK;
+}
+
+int jacobi_batch_set_tuning(jacobi_batch_t b, int t_depth, int rows, int use_graph) {
+    int rc = batch_check(b);
+    if (rc) return rc;
+    const int md = max_depth(2, b->dtype);
+    if (t_depth < 0 || t_depth > md)
+        return fail(JACOBI_E_INVAL, "t_depth must be in [0, %d] (got %d)", md, t_depth);
+    if (rows < 0 || (rows > 0 && rows < kMinRows) || rows > (1 << 20))
+        return fail(JACOBI_E_INVAL, "rows must be 0 or in [%d, 2^20] (got %d)", kMinRows, rows);
+    b->depth = t_depth;
+    b->rows = rows;
+    b->use_graph = use_graph ? 1 : 0;
+    batch_drop_graph(b);
+    return JACOBI_OK;
+}
+
+int jacobi_batch_get_tuning(jacobi_batch_t b, int *t_depth, int *rows, int *use_graph) {
+    int rc = batch_check(b);
+    if (rc) return rc;
+    if (t_depth) *t_depth = batch_depth(b);
+    if (rows) *rows = batch_rows(b);
+    if (use_graph) *use_graph = b->use_graph;
+    return JACOBI_OK;
+}
+
+int jacobi_batch_solve(jacobi_batch_t b, double rel_tol, int64_t max_sweeps, int64_t check_every,
+                       int64_t *sweeps, double *rel, int *status) {
+    int rc = batch_check(b);
+    if (rc) return rc;
+    if (max_sweeps < 0) return fail(JACOBI_E_INVAL, "max_sweeps must be >= 0");
+    if (check_every < 1) return fail(JACOBI_E_INVAL, "check_every must be >= 1");
+    if (!(rel_tol >= 0.0)) return fail(JACOBI_E_INVAL, "rel_tol must be >= 0");
+    for (int i = 0; i < b->count; ++i)
+        if (!b->grid_set[i]) return fail(JACOBI_E_STATE, "grid %d has no state", i);
+    return b->dtype == JACOBI_F32 ? batch_solve<float>(b, rel_tol, max_sweeps, check_every, sweeps, rel, status)
+                                  : batch_solve<double>(b, rel_tol, max_sweeps, check_every, sweeps, rel, status);
+}
+
+int jacobi_batch_autotune(jacobi_batch_t b, int64_t check_every, int *t_depth, int *rows) {
+    int rc = batch_check(b);
+    if (rc) return rc;
+    if (check_every < 1 || check_every > (1 << 20)) return fail(JACOBI_E_INVAL, "check_every out of range");
+    static const int kRows[] = {16, 24, 32, 48, 64, 96, 128, 192};
+    const int *list;
+    const int nd = jac::march2d_depths(b->dtype, &list);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "event create");
+    HIP_TRY(hipEventCreate(&e1), "event create");
+    const int saved_graph = b->use_graph;
+    float best = 1e30f;
+    int bd = 0, br = 0;
+    for (int i = 0; i < nd && !rc; ++i) {
+        for (int r : kRows) {
+            b->depth = list[i];
+            b->rows = r;
+            b->use_graph = 0;
+            rc = b->dtype == JACOBI_F32 ? batch_tables<float>(b) : batch_tables<double>(b);
+            if (rc) break;
+            HIP_TRY(jac::launch_batch_init(b->count, b->st, b->stream), "batch init launch");
+            rc = b->dtype == JACOBI_F32 ? batch_interval<float>(b, check_every, 0.0, false)
+                                        : batch_interval<double>(b, check_every, 0.0, false);
+            if (rc) break;
+            if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = JACOBI_E_HIP; break; }
+            rc = b->dtype == JACOBI_F32 ? batch_interval<float>(b, check_every, 0.0, false)
+                                        : batch_interval<double>(b, check_every, 0.0, false);
+            if (rc) break;
+            float t = 0.0f;
+            if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+                rc = fail(JACOBI_E_HIP, "batch autotune timing failed");
+                break;
+            }
+            if (t < best) {
+                best = t;
+                bd = list[i];
+                br = r;
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    b->use_graph = saved_graph;
+    // the grids' buffers served as scratch
+    for (int i = 0; i < b->count; ++i) b->grid_set[i] = 0;
+    if (rc) return rc;
+    b->depth = bd;
+    b->rows = br;
+    batch_drop_graph(b);
+    if (t_depth) *t_depth = bd;
+    if (rows) *rows = br;
+    return JACOBI_OK;
+}
+
+}  // extern "C"

@@ -37,6 +37,28 @@ struct Geom {
     int64_t nblocks;
 };
 
+// One grid of a batch, as the batched pass kernel sees it.
+struct BatchGrid {
+    Geom g;
+    void *u[2];     // the two state buffers
+    const void *b;  // blocked source
+    int nseg;       // tiles per strip at the batch's tile height
+    int pad;
+};
+
+// Device-side state of a batched solve (arrays of one entry per grid).
+struct BatchState {
+    int *active;          // 1 while the grid still sweeps
+    int *status;          // 0 running, 1 converged, 2 max sweeps, 3 diverged
+    int *final_buf;       // state buffer holding the grid's final state
+    long long *sweeps;    // sweeps of the final state
+    double *rel;          // last relative residual
+    double *res0;         // residual of the initial state
+    double *res;          // last residual
+    int *pass_count;      // passes done (parity of the current buffer)
+    long long *k_now;     // sweeps done by the active grids
+};
+
 // Block index and local coordinate of global coordinate v in [-1, n] along an
 // axis with extent e and nb blocks: -1 belongs to block 0 (its low halo),
 // n to the last block (its high halo).

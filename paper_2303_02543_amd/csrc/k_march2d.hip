@@ -314,8 +314,8 @@ __device__ __forceinline__ void m2_steps(const Geom &g, const R *__restrict__ ui
 template <typename R, int T, int MODE, bool RINGX>
 __device__ __forceinline__ void m2_body(const Geom &g, const R *__restrict__ uin,
                                         R *__restrict__ uout, const R *__restrict__ bsrc,
-                                        double *__restrict__ res, double *__restrict__ gacc,
-                                        const MLane &L, int r0, int wid) {
+                                        double *__restrict__ res_slot,
+                                        double *__restrict__ gacc, const MLane &L, int r0) {
     using S = M2<R, T>;
     MRegs<R, T> m;
 #pragma unroll
@@ -339,39 +339,33 @@ __device__ __forceinline__ void m2_body(const Geom &g, const R *__restrict__ uin
     lc.init(g, r0);
     sc.init(g, r0 - T);
     m2_load<R, T, MODE, RINGX, 0, 0>(g, uin, bsrc, gacc, L, m, lc, 0);  // row r0 -> slot 0
-    const bool want_res = res != nullptr;
+    const bool want_res = res_slot != nullptr;
     int sr = 0;  // LDS source slot of the current row
     for (int base = r0; base <= L.r1; base += S::U)
         m2_steps<R, T, MODE, RINGX, 0>(g, uin, uout, bsrc, gacc, want_res, L, m, base, lc, sc, sr);
     if (want_res) {
         const double a = wave_sum(m.acc);
-        if ((threadIdx.x & 63) == 0) res[wid] = a;
+        if ((threadIdx.x & 63) == 0) *res_slot = a;
     }
 }
 
-// uout may be NULL (no stores: residual only); res may be NULL (no residual);
-// gacc is the FP64 accumulator of the adjoint pass (MODE_ADJOINT only).
+// One work item (wave): strip/tile number `wid` of a grid with `nseg` tiles
+// per strip.  wid is wave-uniform.  res_slot: where the wave's residual
+// partial goes (NULL: none).  bs_wave: the wave's LDS source ring.
 template <typename R, int T, int MODE>
-__global__ __launch_bounds__(256) void k_march2d(Geom g, const R *__restrict__ uin,
-                                                 R *__restrict__ uout,
-                                                 const R *__restrict__ bsrc,
-                                                 double *__restrict__ res,
-                                                 double *__restrict__ gacc, int nseg, int rows,
-                                                 int nwork) {
+__device__ __forceinline__ void m2_run(const Geom &g, const R *__restrict__ uin,
+                                       R *__restrict__ uout, const R *__restrict__ bsrc,
+                                       double *__restrict__ res_slot, double *__restrict__ gacc,
+                                       int wid, int nseg, int rows, Chunk<R, M2<R, T>::V> *bs_wave) {
     using S = M2<R, T>;
     constexpr bool SRC = MODE == MODE_POISSON;
     constexpr int V = S::V;
-    // per wave: a ring of RB source rows, one 16-byte chunk per lane each
-    __shared__ Chunk<R, V> bsm[SRC ? 4 * S::RB * 64 : 1];
     const int lane = threadIdx.x & 63;
-    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int wid = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (wid >= nwork) return;
     const int strip = wid / nseg, seg = wid % nseg;
     const int nx = g.n[0], ny = g.n[1];
     const int a = strip * S::OW - S::A0;  // first column held by the strip
     MLane L;
-    L.bs = SRC ? (void *)&bsm[(threadIdx.x >> 6) * S::RB * 64 + lane] : nullptr;
+    L.bs = SRC ? (void *)(bs_wave + lane) : nullptr;
     L.oy0 = seg * rows;
     L.oy1 = L.oy0 + rows < ny ? L.oy0 + rows : ny;
     L.r1 = L.oy1 - 1 + T;
@@ -404,9 +398,61 @@ __global__ __launch_bounds__(256) void k_march2d(Geom g, const R *__restrict__ u
     const bool ringx = a < 0 || a + S::W > nx;
     const int r0 = L.oy0 - T;
     if (ringx)
-        m2_body<R, T, MODE, true>(g, uin, uout, bsrc, res, gacc, L, r0, wid);
+        m2_body<R, T, MODE, true>(g, uin, uout, bsrc, res_slot, gacc, L, r0);
     else
-        m2_body<R, T, MODE, false>(g, uin, uout, bsrc, res, gacc, L, r0, wid);
+        m2_body<R, T, MODE, false>(g, uin, uout, bsrc, res_slot, gacc, L, r0);
+}
+
+// uout may be NULL (no stores: residual only); res may be NULL (no residual);
+// gacc is the FP64 accumulator of the adjoint pass (MODE_ADJOINT only).
+template <typename R, int T, int MODE>
+__global__ __launch_bounds__(256) void k_march2d(Geom g, const R *__restrict__ uin,
+                                                 R *__restrict__ uout,
+                                                 const R *__restrict__ bsrc,
+                                                 double *__restrict__ res,
+                                                 double *__restrict__ gacc, int nseg, int rows,
+                                                 int nwork) {
+    using S = M2<R, T>;
+    constexpr bool SRC = MODE == MODE_POISSON;
+    // per wave: a ring of RB source rows, one 16-byte chunk per lane each
+    __shared__ Chunk<R, S::V> bsm[SRC ? 4 * S::RB * 64 : 1];
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int wid = __builtin_amdgcn_readfirstlane(lb * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    if (wid >= nwork) return;
+    m2_run<R, T, MODE>(g, uin, uout, bsrc, res ? res + wid : nullptr, gacc, wid, nseg, rows,
+                       &bsm[SRC ? (threadIdx.x >> 6) * S::RB * 64 : 0]);
+}
+
+// Batched pass: the work items of all grids of a batch in one launch.  Work
+// item w belongs to grid gi with prefix[gi] <= w < prefix[gi+1]; inactive
+// grids (stopped by the convergence test) skip their items.  All active
+// grids advance together, so the input buffer is u[pass_count & 1].
+template <typename R, int T>
+__global__ __launch_bounds__(256) void k_march2d_batch(const BatchGrid *__restrict__ grids,
+                                                       const int *__restrict__ prefix, int ngrids,
+                                                       const int *__restrict__ active,
+                                                       const int *__restrict__ pass_count,
+                                                       double *__restrict__ res, int store,
+                                                       int rows, int nwork) {
+    using S = M2<R, T>;
+    __shared__ Chunk<R, S::V> bsm[4 * S::RB * 64];
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int wid = __builtin_amdgcn_readfirstlane(lb * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    if (wid >= nwork) return;
+    int lo = 0, hi = ngrids;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= wid) lo = mid; else hi = mid;
+    }
+    const int gi = __builtin_amdgcn_readfirstlane(lo);
+    if (!active[gi]) return;
+    const Geom g = grids[gi].g;
+    const int par = *pass_count & 1;
+    const R *uin = (const R *)grids[gi].u[par];
+    R *uout = store ? (R *)grids[gi].u[par ^ 1] : nullptr;
+    m2_run<R, T, MODE_POISSON>(g, uin, uout, (const R *)grids[gi].b, res ? res + wid : nullptr,
+                               nullptr, wid - prefix[gi], grids[gi].nseg, rows,
+                               &bsm[(threadIdx.x >> 6) * S::RB * 64]);
 }
 
 template <typename R, int T>
@@ -536,6 +582,57 @@ hipError_t launch_sweep2d_march<double>(const Geom &g, const void *uin, void *uo
     }
 }
 
+template <typename R>
+int64_t march2d_batch_work(const Geom &g, int depth, int rows, int *nseg) {
+    switch (depth) {
+    case 1: return m2_nwork<R, 1>(g, rows, nseg);
+    case 2: return m2_nwork<R, 2>(g, rows, nseg);
+    case 3: return m2_nwork<R, 3>(g, rows, nseg);
+    case 4: return m2_nwork<R, 4>(g, rows, nseg);
+    case 5: return m2_nwork<R, 5>(g, rows, nseg);
+    case 6: return m2_nwork<R, 6>(g, rows, nseg);
+    case 7: return m2_nwork<R, 7>(g, rows, nseg);
+    case 8: return m2_nwork<R, 8>(g, rows, nseg);
+    default: return -1;
+    }
+}
+
+template <typename R, int T>
+static hipError_t m2b_launch_t(const BatchGrid *grids, const int *prefix, int ngrids,
+                               const int *active, const int *pass_count, double *res, bool store,
+                               int rows, int nwork, hipStream_t st) {
+    const int grid = (nwork + 3) / 4;
+    hipLaunchKernelGGL((k_march2d_batch<R, T>), dim3(grid), dim3(256), 0, st, grids, prefix,
+                       ngrids, active, pass_count, res, store ? 1 : 0, rows, nwork);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_march2d_batch(const BatchGrid *grids, const int *prefix, int ngrids,
+                                const int *active, const int *pass_count, double *res, bool store,
+                                int depth, int rows, int nwork, hipStream_t st) {
+    if (nwork <= 0) return hipSuccess;
+    switch (depth) {
+    case 1: return m2b_launch_t<R, 1>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
+    case 2: return m2b_launch_t<R, 2>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
+    case 3: return m2b_launch_t<R, 3>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
+    case 4: return m2b_launch_t<R, 4>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
+    case 5: return m2b_launch_t<R, 5>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
+    case 6: return m2b_launch_t<R, 6>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
+    case 7: return m2b_launch_t<R, 7>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
+    case 8: return m2b_launch_t<R, 8>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template int64_t march2d_batch_work<float>(const Geom &, int, int, int *);
+template int64_t march2d_batch_work<double>(const Geom &, int, int, int *);
+template hipError_t launch_march2d_batch<float>(const BatchGrid *, const int *, int, const int *,
+                                                const int *, double *, bool, int, int, int,
+                                                hipStream_t);
+template hipError_t launch_march2d_batch<double>(const BatchGrid *, const int *, int, const int *,
+                                                 const int *, double *, bool, int, int, int,
+                                                 hipStream_t);
 template int64_t march2d_work_items<float>(const Geom &, int, int);
 template int64_t march2d_work_items<double>(const Geom &, int, int);
 template int march2d_waves_per_cu<float>(int, int);

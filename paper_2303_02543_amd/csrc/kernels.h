@@ -52,6 +52,23 @@ int64_t march2d_strips(const Geom &g, int depth);
 // Depths compiled for the 2D march kernel, ascending; returns the count.
 int march2d_depths(int dtype, const int **list);
 
+// Batched pass over the grids of a batch (Poisson kernels; see
+// k_march2d_batch).  nwork = prefix[ngrids]; res: one partial per work item
+// (NULL: no residual); store = false: residual only.
+template <typename R>
+hipError_t launch_march2d_batch(const BatchGrid *grids, const int *prefix, int ngrids,
+                                const int *active, const int *pass_count, double *res, bool store,
+                                int depth, int rows, int nwork, hipStream_t st);
+// Work items of one grid at this depth / tile height; tiles per strip in *nseg.
+template <typename R>
+int64_t march2d_batch_work(const Geom &g, int depth, int rows, int *nseg);
+
+// Batched-solver bookkeeping (k_batch.hip).
+hipError_t launch_batch_init(int count, const BatchState &st, hipStream_t s);
+hipError_t launch_batch_advance(const BatchState &st, int sweeps, hipStream_t s);
+hipError_t launch_batch_check(const int *prefix, const double *partials, int count,
+                              const BatchState &st, double tol, bool final_check, hipStream_t s);
+
 // Sum n partials in a fixed order and write sqrt(total) to *out.
 hipError_t launch_residual_final(const double *partials, int n, double *out, hipStream_t st);
 

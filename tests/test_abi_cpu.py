@@ -102,6 +102,28 @@ def test_null_pointers_and_handles_rejected():
     assert L.jacobi_destroy(None) == jb.JACOBI_OK
 
 
+def test_batch_arguments_rejected():
+    L = jb.lib()
+    out = ctypes.c_void_p()
+    sz = ctypes.c_size_t()
+    good = jb._arr64([300, 257, 64, 64])
+    assert L.jacobi_batch_workspace_bytes(2, good, 64, 0, ctypes.byref(sz)) == jb.JACOBI_OK
+    assert sz.value > 2 * (302 * 259 + 66 * 66) * 4
+    assert L.jacobi_batch_workspace_bytes(0, good, 64, 0, ctypes.byref(sz)) == jb.JACOBI_E_INVAL
+    assert L.jacobi_batch_workspace_bytes(2, None, 64, 0, ctypes.byref(sz)) == jb.JACOBI_E_INVAL
+    assert L.jacobi_batch_workspace_bytes(2, good, 4, 0, ctypes.byref(sz)) == jb.JACOBI_E_INVAL
+    assert L.jacobi_batch_workspace_bytes(2, jb._arr64([0, 5, 5, 5]), 64, 0,
+                                          ctypes.byref(sz)) == jb.JACOBI_E_INVAL
+    assert L.jacobi_batch_create(2, good, 64, 0, None, 1 << 30, None,
+                                 ctypes.byref(out)) == jb.JACOBI_E_INVAL
+    assert L.jacobi_batch_destroy(None) == jb.JACOBI_OK
+    assert L.jacobi_batch_solve(None, 1e-6, 10, 5, None, None, None) == jb.JACOBI_E_INVAL
+    assert L.jacobi_batch_set_tuning(None, 1, 8, 1) == jb.JACOBI_E_INVAL
+    assert L.jacobi_adjoint_begin(None, None, None) == jb.JACOBI_E_INVAL
+    assert L.jacobi_adjoint_sweep(None, 1) == jb.JACOBI_E_INVAL
+    assert L.jacobi_adjoint_end(None, 1.0, None, None) == jb.JACOBI_E_INVAL
+
+
 def test_strerror_and_depths():
     assert jb.jacobi_strerror(0) == "success"
     assert "invalid" in jb.jacobi_strerror(jb.JACOBI_E_INVAL)

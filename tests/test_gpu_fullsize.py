@@ -1,0 +1,191 @@
+"""Parity at the workloads' full sizes, in the launch configurations the
+benchmark uses (autotuned schedule, same call sequence).  The oracle computes
+each full run once on the host's cores (FP32 runs against the oracle's FP32
+twin bit for bit, and against the FP64 oracle within 1e-5 norm-relative)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+from gpu_util import bits_equal, first_mismatch, norm_rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def residual_history(U0, b, K, R):
+    res = []
+    U = U0
+    k = 0
+    res.append(oracle.residual(U, b))
+    while k < K:
+        step = min(R, K - k)
+        U = oracle.sweep(U, b, step)
+        k += step
+        res.append(oracle.residual(U, b))
+    return U, np.array(res)
+
+
+def test_poisson2d_8192_full(device):
+    """2D Poisson 8192^2 FP32, 16x16 blocks, 1000 sweeps, residual every 50:
+    the whole final state bit-exact with the FP32 oracle twin, every residual
+    within 1e-12, and the state within 1e-5 of the FP64 oracle."""
+    import torch
+    import paper_2303_02543_amd as jb
+    n, K, R = 8192, 1000, 50
+    f32 = synthetic.gaussian_sum(n, 2, 2).astype(np.float32)
+    U0 = np.zeros((n + 2, n + 2), dtype=np.float32)
+    h2 = synthetic.spacing2(n)
+    s = jb.Solver((n, n), (16, 16), torch.float32, device=device)
+    try:
+        d, r, fl = s.autotune(R, with_source=True)
+        say("8192^2 schedule depth=%d rows=%d flags=%d" % (d, r, fl))
+        s.set_source(torch.from_numpy(f32).to(device), h2)
+        s.set_state(torch.from_numpy(U0).to(device))
+        res = s.solve(K, R).cpu().numpy()
+        got = s.get_state().cpu().numpy()
+    finally:
+        s.close()
+    b32 = oracle.scale_source(f32, h2, np.float32)
+    want, ores = residual_history(U0, b32, K, R)
+    if not bits_equal(got, want):
+        raise AssertionError("8192^2 not bit-exact: %s" % (first_mismatch(got, want),))
+    np.testing.assert_allclose(res, ores, rtol=1e-12, atol=0)
+    b64 = oracle.scale_source(f32.astype(np.float64), h2, np.float64)
+    ref = oracle.sweep(U0.astype(np.float64), b64, K)
+    err = norm_rel_err(got, ref)
+    say("8192^2 FP32 vs FP64 rel err %.3e" % err)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_poisson3d_512_full(device, dtype):
+    """3D Poisson 512^3, 8x8x8 blocks of 64^3, 200 sweeps, residual every 20."""
+    import torch
+    import paper_2303_02543_amd as jb
+    n, K, R = 512, 200, 20
+    U0, f = synthetic.poisson3d_c3(n)
+    U0 = U0.astype(dtype)
+    fd = f.astype(dtype)
+    h2 = synthetic.spacing2(n)
+    tdt = torch.float32 if dtype == np.float32 else torch.float64
+    s = jb.Solver((n, n, n), (8, 8, 8), tdt, device=device)
+    try:
+        s.set_source(torch.from_numpy(fd).to(device), h2)
+        s.set_state(torch.from_numpy(U0).to(device))
+        res = s.solve(K, R).cpu().numpy()
+        got = s.get_state().cpu().numpy()
+    finally:
+        s.close()
+    b = oracle.scale_source(fd, h2, dtype)
+    want, ores = residual_history(U0, b, K, R)
+    assert bits_equal(got, want), "512^3 %s not bit-exact" % np.dtype(dtype).name
+    np.testing.assert_allclose(res, ores, rtol=1e-12, atol=0)
+    if dtype == np.float32:
+        b64 = oracle.scale_source(fd.astype(np.float64), h2, np.float64)
+        err = norm_rel_err(got, oracle.sweep(U0.astype(np.float64), b64, K))
+        say("512^3 FP32 vs FP64 rel err %.3e" % err)
+        assert err <= 1e-5
+
+
+def test_batched_64_grids_sampled(device):
+    """The 64-grid batch as the benchmark runs it; the smallest, the largest
+    and two more grids are checked against the oracle's own stop-rule solve
+    (5000 sweeps, residual every 50, tolerance 1e-6) bit for bit."""
+    import torch
+    import paper_2303_02543_amd as jb
+    sizes = [int(n) for n in synthetic.batched_sizes()]
+    srcs = [synthetic.batched_source(n, g).astype(np.float32) for g, n in enumerate(sizes)]
+    B = jb.Batch([(n, n) for n in sizes], torch.float32, block=512, device=device)
+    try:
+        d, r = B.autotune(50)
+        B.set_tuning(d, r, True)
+        say("batch schedule depth=%d rows=%d" % (d, r))
+        for g, n in enumerate(sizes):
+            B.set_grid(g, torch.zeros((n + 2, n + 2), dtype=torch.float32, device=device),
+                       torch.from_numpy(srcs[g]).to(device), synthetic.spacing2(n))
+        sw, rl, st = B.solve(1e-6, 5000, 50)
+        picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 40})
+        finals = {g: B.get_grid(g).cpu().numpy() for g in picks}
+    finally:
+        B.close()
+    for g in picks:
+        n = sizes[g]
+        say("batch grid %d n=%d" % (g, n))
+        b32 = oracle.scale_source(srcs[g], synthetic.spacing2(n), np.float32)
+        out = oracle.solve(np.zeros((n + 2, n + 2), np.float32), b32, 5000, 50, 1e-6)
+        assert sw[g] == out["sweeps"] and jb.STATUS_NAMES[st[g]] == out["status"]
+        assert math.isclose(rl[g], out["rel"], rel_tol=1e-12)
+        assert bits_equal(finals[g], out["u"]), "batched grid %d" % g
+
+
+@pytest.fixture(scope="module")
+def adjoint_4096(device):
+    """Gradients of L = 1/2||u_K - t||^2 (4096^2 FP32, K = 500, C = 50) through
+    JacobiK, and the FP64 oracle's gradients on the same FP32-rounded inputs."""
+    import torch
+    import paper_2303_02543_amd as jb
+    from paper_2303_02543_amd.autograd import JacobiK
+    n, K, C = 4096, 500, 50
+    U0, f, t = synthetic.adjoint_c5(n)
+    U0, f, t = U0.astype(np.float32), f.astype(np.float32), t.astype(np.float32)
+    h2 = synthetic.spacing2(n)
+    s = jb.Solver((n, n), (8, 8), torch.float32, device=device)
+    try:
+        fT = torch.from_numpy(f).to(device).requires_grad_(True)
+        UT = torch.from_numpy(U0).to(device).requires_grad_(True)
+        uK = JacobiK.apply(fT, UT, s, K, h2, C)
+        loss = 0.5 * ((uK[1:-1, 1:-1] - torch.from_numpy(t).to(device)) ** 2).sum()
+        loss.backward()
+        gf, gU = fT.grad.cpu().numpy(), UT.grad.cpu().numpy()
+    finally:
+        s.close()
+    U64, f64, t64 = U0.astype(np.float64), f.astype(np.float64), t.astype(np.float64)
+    L, dLdf, dLdU0 = oracle.gradients2d(U64, f64, h2, t64, K)
+    return dict(n=n, K=K, h2=h2, U0=U64, f=f64, t=t64, gf=gf, gU=gU, L=L, dLdf=dLdf,
+                dLdU0=dLdU0, loss=float(loss))
+
+
+def test_adjoint_4096_vs_fp64_oracle(adjoint_4096):
+    a = adjoint_4096
+    assert math.isclose(a["loss"], a["L"], rel_tol=1e-5)
+    ef = np.max(np.abs(a["gf"] - a["dLdf"])) / np.max(np.abs(a["dLdf"]))
+    ring = np.zeros_like(a["gU"], dtype=bool)
+    ring[[0, -1], :] = True
+    ring[:, [0, -1]] = True
+    eg = np.max(np.abs(a["gU"][ring] - a["dLdU0"][ring])) / np.max(np.abs(a["dLdU0"][ring]))
+    eu = np.max(np.abs(a["gU"][1:-1, 1:-1] - a["dLdU0"][1:-1, 1:-1])) / \
+        np.max(np.abs(a["dLdU0"][1:-1, 1:-1]))
+    say("adjoint 4096 errors: f %.2e, g %.2e, u0 %.2e" % (ef, eg, eu))
+    assert ef <= 1e-5 and eg <= 1e-5 and eu <= 1e-5
+
+
+@pytest.mark.parametrize("part", ["f0", "f1", "g0", "g1"])
+def test_adjoint_4096_central_differences(adjoint_4096, part):
+    """Central differences (eps = 1e-3, FP64 oracle runs, loss differenced
+    cell by cell) on 32 source and 32 boundary entries (16 per test)."""
+    a = adjoint_4096
+    f_idx, g_idx = synthetic.fd_picks(a["n"], count=32, seed=8)
+    idx = (f_idx if part[0] == "f" else g_idx)[16 * int(part[1]):16 * int(part[1]) + 16]
+    fd, dev, orc = [], [], []
+    for i in idx:
+        if part[0] == "f":
+            fd.append(oracle.fd_grad_source(a["U0"], a["f"], a["h2"], a["t"], a["K"], i, 1e-3))
+            dev.append(a["gf"][i])
+            orc.append(a["dLdf"][i])
+        else:
+            fd.append(oracle.fd_grad_state(a["U0"], a["f"], a["h2"], a["t"], a["K"], i, 1e-3))
+            dev.append(a["gU"][i])
+            orc.append(a["dLdU0"][i])
+    fd, dev, orc = np.array(fd), np.array(dev), np.array(orc)
+    scale = np.max(np.abs(fd))
+    say("FD %s: max |oracle - fd| / max|fd| = %.2e, device %.2e" % (
+        part, np.max(np.abs(orc - fd)) / scale, np.max(np.abs(dev - fd)) / scale))
+    np.testing.assert_allclose(orc, fd, rtol=1e-4, atol=1e-7 * scale)
+    assert np.max(np.abs(dev - fd)) <= 1e-5 * scale
