@@ -67,7 +67,10 @@ enum jacobi_flags {
      * flag the sweep reads face neighbours' cells directly from their blocks
      * (the exchange fused into the sweep's loads) and may do several sweeps
      * per pass. */
-    JACOBI_FLAG_EXPLICIT_HALO = 1
+    JACOBI_FLAG_EXPLICIT_HALO = 1,
+    /* Store pass outputs with the non-temporal hint (not kept in the caches).
+     * A pure performance choice; results are identical either way. */
+    JACOBI_FLAG_NT_STORES = 2
 };
 
 /* ---------------------------------------------------------------- set-up */

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libjacobi.so")
 JACOBI_F32 = 0
 JACOBI_F64 = 1
 JACOBI_FLAG_EXPLICIT_HALO = 1
+JACOBI_FLAG_NT_STORES = 2
 
 JACOBI_RUNNING = 0
 JACOBI_CONVERGED = 1

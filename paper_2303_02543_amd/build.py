@@ -18,8 +18,8 @@ LIB = os.path.join(HERE, "libjacobi.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
-SOURCES = ["jacobi_abi.hip", "k_layout.hip", "k_sweep.hip", "k_march2d.hip", "k_residual.hip",
-           "k_batch.hip"]
+SOURCES = ["jacobi_abi.hip", "k_layout.hip", "k_sweep.hip", "k_march2d.hip", "k_march3d.hip",
+           "k_residual.hip", "k_batch.hip"]
 HEADERS = ["jacobi_internal.h", "kernels.h", "device_util.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -22,6 +22,17 @@ __device__ __forceinline__ X &at_mut(void *base, uint32_t byte_off) {
     return *reinterpret_cast<X *>(reinterpret_cast<char *>(base) + byte_off);
 }
 
+// 16-byte store with the non-temporal hint (the line is not kept in the
+// caches on its way to memory).
+template <typename X>
+__device__ __forceinline__ void store_nt16(X *p, const X &v) {
+    static_assert(sizeof(X) == 16, "16-byte stores only");
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 t;
+    __builtin_memcpy(&t, &v, 16);
+    __builtin_nontemporal_store(t, reinterpret_cast<u32x4 *>(p));
+}
+
 // Whole-wave lane shifts through DPP (wave_shr:1 / wave_shl:1).  All 64
 // lanes must be active.
 // shift_up: lane i receives src of lane i-1; lane 0 keeps `old`.

@@ -123,6 +123,12 @@ int plan(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, Geom *
     // least 32 columns, tiles of at least kMinRows rows), or one per
     // workgroup of the standalone residual kernel
     size_t cap = ((size_t)g->n[0] / 32 + 2) * ((size_t)g->n[1] * g->n[2] / kMinRows + 2);
+    if (ndim == 3) {
+        // 3D pass: one work item per (strip of >= 128 columns, row, z segment)
+        const size_t c3 = ((size_t)g->n[0] / 128 + 1) * (size_t)g->n[1] *
+                          ((size_t)g->n[2] / kMinRows + 1);
+        if (c3 > cap) cap = c3;
+    }
     if (cap < (size_t)jac::kResidualGroups) cap = jac::kResidualGroups;
     l->part_cap = cap;
     l->off_part = off;
@@ -194,7 +200,7 @@ int balanced_rows(const jacobi_s *h, int depth, int mode, int rounds) {
 // explicit halos (depth 1) for 3D.
 int default_depth(const jacobi_s *h) {
     if (h->g.ndim == 3) return 1;
-    return h->dtype == JACOBI_F32 ? 7 : 4;
+    return h->dtype == JACOBI_F32 ? 8 : 4;
 }
 
 int default_rows(const jacobi_s *h) {
@@ -247,9 +253,22 @@ int do_halo(jacobi_t h) {
     return JACOBI_OK;
 }
 
+int zseg_of(const jacobi_s *h) { return h->rows > 0 ? h->rows : 32; }
+
 template <typename R>
 int do_residual(jacobi_t h, double *out) {
     const void *b = h->has_source ? h->b : nullptr;
+    if (h->g.ndim == 3) {
+        const int64_t nw = jac::march3d_work_items<R>(h->g, zseg_of(h));
+        if ((size_t)nw > h->lay.part_cap) return fail(JACOBI_E_INVAL, "partials overflow");
+        int64_t nwork = 0;
+        HIP_TRY(jac::launch_march3d<R>(h->g, h->u[h->cur], nullptr, b, h->partials, zseg_of(h),
+                                       h->stream, &nwork),
+                "residual launch");
+        HIP_TRY(jac::launch_residual_final(h->partials, (int)nwork, out, h->stream),
+                "residual launch");
+        return JACOBI_OK;
+    }
     if (h->g.ndim == 2) {
         // one residual-only pass of the march kernel (no stores)
         const int rows = balanced_rows(h, 1, h->has_source ? 1 : 0, 1);
@@ -273,7 +292,30 @@ int do_residual(jacobi_t h, double *out) {
 template <typename R>
 int do_sweep(jacobi_t h, int64_t n, double *res_first) {
     const void *b = h->has_source ? h->b : nullptr;
-    const bool explicit_halo = (h->flags & JACOBI_FLAG_EXPLICIT_HALO) || h->g.ndim == 3;
+    const bool explicit_halo = (h->flags & JACOBI_FLAG_EXPLICIT_HALO) != 0;
+    if (h->g.ndim == 3 && !explicit_halo && n > 0) {
+        // fused 3D passes, one sweep each; the first also sums the residual
+        const int zseg = zseg_of(h);
+        for (int64_t k = 0; k < n; ++k) {
+            double *part = (k == 0 && res_first) ? h->partials : nullptr;
+            if (part && (size_t)jac::march3d_work_items<R>(h->g, zseg) > h->lay.part_cap)
+                return fail(JACOBI_E_INVAL, "partials overflow");
+            int rc = prof_begin(h);
+            if (rc) return rc;
+            int64_t nwork = 0;
+            HIP_TRY(jac::launch_march3d<R>(h->g, h->u[h->cur], h->u[h->cur ^ 1], b, part, zseg,
+                                           h->stream, &nwork, h->flags & JACOBI_FLAG_NT_STORES),
+                    "sweep launch");
+            rc = prof_end(h, 1);
+            if (rc) return rc;
+            if (part)
+                HIP_TRY(jac::launch_residual_final(part, (int)nwork, res_first, h->stream),
+                        "residual launch");
+            h->cur ^= 1;
+        }
+        HIP_TRY(jac::launch_halo_exchange<R>(h->g, h->u[h->cur], h->stream), "halo exchange launch");
+        return JACOBI_OK;
+    }
     if (explicit_halo || n == 0) {
         if (res_first) {
             int rc = do_residual<R>(h, res_first);
@@ -312,7 +354,8 @@ int do_sweep(jacobi_t h, int64_t n, double *res_first) {
         if (rc) return rc;
         int64_t nwork = 0;
         HIP_TRY(jac::launch_sweep2d_march<R>(h->g, h->u[h->cur], h->u[h->cur ^ 1], b, part, nullptr, t,
-                                             rows, h->stream, &nwork),
+                                             rows, h->stream, &nwork,
+                                             h->flags & JACOBI_FLAG_NT_STORES),
                 "sweep launch");
         rc = prof_end(h, t);
         if (rc) return rc;
@@ -597,7 +640,8 @@ int jacobi_set_tuning(jacobi_t h, int t_depth, int rows, int flags) {
         return fail(JACOBI_E_INVAL, "t_depth must be in [0, %d] (got %d)", md, t_depth);
     if (rows < 0 || (rows > 0 && rows < kMinRows) || rows > (1 << 20))
         return fail(JACOBI_E_INVAL, "rows must be 0 or in [%d, 2^20] (got %d)", kMinRows, rows);
-    if (flags & ~JACOBI_FLAG_EXPLICIT_HALO) return fail(JACOBI_E_INVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(JACOBI_FLAG_EXPLICIT_HALO | JACOBI_FLAG_NT_STORES))
+        return fail(JACOBI_E_INVAL, "unknown flags 0x%x", flags);
     h->depth = t_depth;
     h->rows = rows;
     h->flags = flags;
@@ -711,6 +755,11 @@ int jacobi_autotune(jacobi_t h, int64_t n_sweeps, int with_source, int *t_depth,
         };
         std::vector<Cand> cands;
         cands.push_back({1, 0, JACOBI_FLAG_EXPLICIT_HALO});
+        if (h->g.ndim == 3) {
+            static const int kZseg[] = {8, 16, 32, 64, 128};
+            for (int z : kZseg)
+                for (int f : {0, (int)JACOBI_FLAG_NT_STORES}) cands.push_back({1, z, f});
+        }
         if (h->g.ndim == 2) {
             const int *list;
             const int nd = jac::march2d_depths(h->dtype, &list);
@@ -725,6 +774,7 @@ int jacobi_autotune(jacobi_t h, int64_t n_sweeps, int with_source, int *t_depth,
                     if (dup) continue;
                     seen.push_back(r);
                     cands.push_back({list[i], r, 0});
+                    cands.push_back({list[i], r, (int)JACOBI_FLAG_NT_STORES});
                 }
             }
         }

@@ -101,6 +101,7 @@ struct MLane {
     bool upd[8];                     // per-element: interior column (ring strips)
     bool st[8];                      // per-element: interior output column (ring strips)
     bool out_lane;                   // lane holds output columns
+    bool nt;                         // non-temporal output stores
     int c;                           // global column of the lane's first element
     void *bs;                        // this lane's slot 0 of the wave's LDS source ring
     int oy0, oy1, r1;
@@ -267,7 +268,10 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
                         Chunk<R, V> o;
 #pragma unroll
                         for (int v = 0; v < V; ++v) o.v[v] = out[v];
-                        at_mut<Chunk<R, V>>(row, L.lane_b) = o;
+                        if (L.nt)
+                            store_nt16(&at_mut<Chunk<R, V>>(row, L.lane_b), o);
+                        else
+                            at_mut<Chunk<R, V>>(row, L.lane_b) = o;
                     }
                 } else {
 #pragma unroll
@@ -356,7 +360,8 @@ template <typename R, int T, int MODE>
 __device__ __forceinline__ void m2_run(const Geom &g, const R *__restrict__ uin,
                                        R *__restrict__ uout, const R *__restrict__ bsrc,
                                        double *__restrict__ res_slot, double *__restrict__ gacc,
-                                       int wid, int nseg, int rows, Chunk<R, M2<R, T>::V> *bs_wave) {
+                                       int wid, int nseg, int rows, Chunk<R, M2<R, T>::V> *bs_wave,
+                                       bool nt) {
     using S = M2<R, T>;
     constexpr bool SRC = MODE == MODE_POISSON;
     constexpr int V = S::V;
@@ -389,6 +394,7 @@ __device__ __forceinline__ void m2_run(const Geom &g, const R *__restrict__ uin,
         L.edge_b = (uint32_t)(((int64_t)bx * g.bstride + g.ax + lx) * (int64_t)sizeof(R));
     }
     L.out_lane = lane >= S::L0 && lane < S::L1;
+    L.nt = nt;
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
         const int x = c + v;
@@ -411,7 +417,7 @@ __global__ __launch_bounds__(256) void k_march2d(Geom g, const R *__restrict__ u
                                                  const R *__restrict__ bsrc,
                                                  double *__restrict__ res,
                                                  double *__restrict__ gacc, int nseg, int rows,
-                                                 int nwork) {
+                                                 int nwork, int nt) {
     using S = M2<R, T>;
     constexpr bool SRC = MODE == MODE_POISSON;
     // per wave: a ring of RB source rows, one 16-byte chunk per lane each
@@ -420,7 +426,7 @@ __global__ __launch_bounds__(256) void k_march2d(Geom g, const R *__restrict__ u
     const int wid = __builtin_amdgcn_readfirstlane(lb * (blockDim.x >> 6) + (threadIdx.x >> 6));
     if (wid >= nwork) return;
     m2_run<R, T, MODE>(g, uin, uout, bsrc, res ? res + wid : nullptr, gacc, wid, nseg, rows,
-                       &bsm[SRC ? (threadIdx.x >> 6) * S::RB * 64 : 0]);
+                       &bsm[SRC ? (threadIdx.x >> 6) * S::RB * 64 : 0], nt != 0);
 }
 
 // Batched pass: the work items of all grids of a batch in one launch.  Work
@@ -452,7 +458,7 @@ __global__ __launch_bounds__(256) void k_march2d_batch(const BatchGrid *__restri
     R *uout = store ? (R *)grids[gi].u[par ^ 1] : nullptr;
     m2_run<R, T, MODE_POISSON>(g, uin, uout, (const R *)grids[gi].b, res ? res + wid : nullptr,
                                nullptr, wid - prefix[gi], grids[gi].nseg, rows,
-                               &bsm[(threadIdx.x >> 6) * S::RB * 64]);
+                               &bsm[(threadIdx.x >> 6) * S::RB * 64], false);
 }
 
 template <typename R, int T>
@@ -467,7 +473,7 @@ static int64_t m2_nwork(const Geom &g, int rows, int *nseg_out) {
 template <typename R, int T>
 static hipError_t m2_launch_t(const Geom &g, const void *uin, void *uout, const void *b,
                               double *res, double *gacc, int rows, hipStream_t st,
-                              int64_t *nwork_out) {
+                              int64_t *nwork_out, int nt) {
     int nseg = 0;
     const int64_t nwork = m2_nwork<R, T>(g, rows, &nseg);
     if (nwork_out) *nwork_out = nwork;
@@ -476,15 +482,15 @@ static hipError_t m2_launch_t(const Geom &g, const void *uin, void *uout, const 
     if (gacc)
         hipLaunchKernelGGL((k_march2d<R, T, MODE_ADJOINT>), dim3(grid), dim3(256), 0, st, g,
                            (const R *)uin, (R *)uout, (const R *)nullptr, (double *)nullptr,
-                           gacc, nseg, rows, (int)nwork);
+                           gacc, nseg, rows, (int)nwork, nt);
     else if (b)
         hipLaunchKernelGGL((k_march2d<R, T, MODE_POISSON>), dim3(grid), dim3(256), 0, st, g,
                            (const R *)uin, (R *)uout, (const R *)b, res, (double *)nullptr, nseg,
-                           rows, (int)nwork);
+                           rows, (int)nwork, nt);
     else
         hipLaunchKernelGGL((k_march2d<R, T, MODE_LAPLACE>), dim3(grid), dim3(256), 0, st, g,
                            (const R *)uin, (R *)uout, (const R *)nullptr, res, (double *)nullptr,
-                           nseg, rows, (int)nwork);
+                           nseg, rows, (int)nwork, nt);
     return hipGetLastError();
 }
 
@@ -555,16 +561,16 @@ int64_t march2d_work_items(const Geom &g, int depth, int rows) {
 template <>
 hipError_t launch_sweep2d_march<float>(const Geom &g, const void *uin, void *uout, const void *b,
                                        double *res, double *gacc, int depth, int rows,
-                                       hipStream_t st, int64_t *nwork) {
+                                       hipStream_t st, int64_t *nwork, int nt) {
     switch (depth) {
-    case 1: return m2_launch_t<float, 1>(g, uin, uout, b, res, gacc, rows, st, nwork);
-    case 2: return m2_launch_t<float, 2>(g, uin, uout, b, res, gacc, rows, st, nwork);
-    case 3: return m2_launch_t<float, 3>(g, uin, uout, b, res, gacc, rows, st, nwork);
-    case 4: return m2_launch_t<float, 4>(g, uin, uout, b, res, gacc, rows, st, nwork);
-    case 5: return m2_launch_t<float, 5>(g, uin, uout, b, res, gacc, rows, st, nwork);
-    case 6: return m2_launch_t<float, 6>(g, uin, uout, b, res, gacc, rows, st, nwork);
-    case 7: return m2_launch_t<float, 7>(g, uin, uout, b, res, gacc, rows, st, nwork);
-    case 8: return m2_launch_t<float, 8>(g, uin, uout, b, res, gacc, rows, st, nwork);
+    case 1: return m2_launch_t<float, 1>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
+    case 2: return m2_launch_t<float, 2>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
+    case 3: return m2_launch_t<float, 3>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
+    case 4: return m2_launch_t<float, 4>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
+    case 5: return m2_launch_t<float, 5>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
+    case 6: return m2_launch_t<float, 6>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
+    case 7: return m2_launch_t<float, 7>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
+    case 8: return m2_launch_t<float, 8>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
     default: return hipErrorInvalidValue;
     }
 }
@@ -572,12 +578,12 @@ hipError_t launch_sweep2d_march<float>(const Geom &g, const void *uin, void *uou
 template <>
 hipError_t launch_sweep2d_march<double>(const Geom &g, const void *uin, void *uout, const void *b,
                                         double *res, double *gacc, int depth, int rows,
-                                        hipStream_t st, int64_t *nwork) {
+                                        hipStream_t st, int64_t *nwork, int nt) {
     switch (depth) {
-    case 1: return m2_launch_t<double, 1>(g, uin, uout, b, res, gacc, rows, st, nwork);
-    case 2: return m2_launch_t<double, 2>(g, uin, uout, b, res, gacc, rows, st, nwork);
-    case 3: return m2_launch_t<double, 3>(g, uin, uout, b, res, gacc, rows, st, nwork);
-    case 4: return m2_launch_t<double, 4>(g, uin, uout, b, res, gacc, rows, st, nwork);
+    case 1: return m2_launch_t<double, 1>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
+    case 2: return m2_launch_t<double, 2>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
+    case 3: return m2_launch_t<double, 3>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
+    case 4: return m2_launch_t<double, 4>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
     default: return hipErrorInvalidValue;
     }
 }

@@ -38,7 +38,7 @@ hipError_t launch_sweep_local(const Geom &g, const void *uin, void *uout, const 
 template <typename R>
 hipError_t launch_sweep2d_march(const Geom &g, const void *uin, void *uout, const void *b,
                                 double *res, double *gacc, int depth, int rows, hipStream_t st,
-                                int64_t *nwork);
+                                int64_t *nwork, int nt = 0);
 // Work items (waves) of one march launch; -1 for an unknown depth.
 template <typename R>
 int64_t march2d_work_items(const Geom &g, int depth, int rows);
@@ -52,6 +52,7 @@ int64_t march2d_strips(const Geom &g, int depth);
 // Depths compiled for the 2D march kernel, ascending; returns the count.
 int march2d_depths(int dtype, const int **list);
 
+// nt != 0: non-temporal output stores.
 // Batched pass over the grids of a batch (Poisson kernels; see
 // k_march2d_batch).  nwork = prefix[ngrids]; res: one partial per work item
 // (NULL: no residual); store = false: residual only.
@@ -62,6 +63,15 @@ hipError_t launch_march2d_batch(const BatchGrid *grids, const int *prefix, int n
 // Work items of one grid at this depth / tile height; tiles per strip in *nseg.
 template <typename R>
 int64_t march2d_batch_work(const Geom &g, int depth, int rows, int *nseg);
+
+// One 3D sweep in one pass over the whole grid (k_march3d.hip), reading face
+// neighbours' cells from their owning blocks; zseg planes per work item.
+// uout may be NULL (residual only); res: one partial per work item or NULL.
+template <typename R>
+hipError_t launch_march3d(const Geom &g, const void *uin, void *uout, const void *b, double *res,
+                          int zseg, hipStream_t st, int64_t *nwork, int nt = 0);
+template <typename R>
+int64_t march3d_work_items(const Geom &g, int zseg);
 
 // Batched-solver bookkeeping (k_batch.hip).
 hipError_t launch_batch_init(int count, const BatchState &st, hipStream_t s);

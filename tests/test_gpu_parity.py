@@ -79,6 +79,9 @@ def test_2d_bit_exact_all_depths(device, dtype, case):
     assert_bits(got, want_l, "2d laplace %s" % (case,))
     got, _ = run_device(U0, f, h2, K, (bx, by), dtype, device, flags=jb.JACOBI_FLAG_EXPLICIT_HALO)
     assert_bits(got, want, "2d explicit halo %s" % (case,))
+    got, _ = run_device(U0, f, h2, K, (bx, by), dtype, device, depth=depths[-1],
+                        flags=jb.JACOBI_FLAG_NT_STORES)
+    assert_bits(got, want, "2d non-temporal stores %s" % (case,))
 
 
 # --------------------------------------------------------------- small 3D
@@ -86,6 +89,8 @@ CASES_3D = [
     (16, 16, 16, 2, 2, 2, 5),
     (13, 9, 11, 1, 2, 3, 7),
     (40, 3, 5, 2, 1, 1, 4),
+    (300, 20, 17, 3, 2, 2, 6),
+    (1, 1, 1, 1, 1, 1, 2),
 ]
 
 
@@ -97,9 +102,16 @@ def test_3d_bit_exact(device, dtype, case):
     U0 = RNG.uniform(0, 1, (nz + 2, ny + 2, nx + 2))
     f = RNG.uniform(-1, 1, (nz, ny, nx))
     h2 = synthetic.spacing2(max(case[:3]))
+    import paper_2303_02543_amd as jb
     want, _ = oracle_run(U0, f, h2, K, dtype)
-    got, _ = run_device(U0, f, h2, K, (bx, by, bz), dtype, device)
-    assert_bits(got, want, "3d %s" % (case,))
+    for rows, flags in ((0, 0), (8, 0), (64, 0), (0, jb.JACOBI_FLAG_EXPLICIT_HALO),
+                        (16, jb.JACOBI_FLAG_NT_STORES)):
+        got, res = run_device(U0, f, h2, K, (bx, by, bz), dtype, device, rows=rows, flags=flags,
+                              check_every=3)
+        assert_bits(got, want, "3d %s rows %d flags %d" % (case, rows, flags))
+        b = oracle.scale_source(np.asarray(f, dtype=dtype), h2, dtype)
+        ores, _ = oracle_residuals(np.asarray(U0, dtype=dtype), b, K, 3)
+        np.testing.assert_allclose(res, ores, rtol=1e-12, atol=0)
     want_l, _ = oracle_run(U0, None, h2, K, dtype)
     got_l, _ = run_device(U0, None, h2, K, (bx, by, bz), dtype, device)
     assert_bits(got_l, want_l, "3d laplace %s" % (case,))
