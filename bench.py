@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--depth", type=int, default=0, help="temporal depth (0 = autotune)")
     ap.add_argument("--rows", type=int, default=0, help="rows per tile (with --depth)")
+    ap.add_argument("--flags", type=int, default=0,
+                    help="schedule flags with --depth (2 = non-temporal stores)")
     ap.add_argument("--explicit-halo", action="store_true",
                     help="exchange halos and sweep block-locally every sweep (depth 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -307,7 +309,7 @@ def main():
     if args.explicit_halo:
         s.set_tuning(1, 0, jb.JACOBI_FLAG_EXPLICIT_HALO)
     elif args.depth > 0:
-        s.set_tuning(args.depth, args.rows, 0)
+        s.set_tuning(args.depth, args.rows, args.flags)
     else:
         s.autotune(CHECK_EVERY, with_source=True)
     depth, rows, flags = s.get_tuning()
@@ -391,6 +393,7 @@ def main():
             "grid": [N, N], "blocks": list(BLOCKS), "sweeps": SWEEPS,
             "check_every": CHECK_EVERY, "t_depth": depth, "rows": rows,
             "explicit_halo": bool(flags & jb.JACOBI_FLAG_EXPLICIT_HALO),
+            "nt_stores": bool(flags & jb.JACOBI_FLAG_NT_STORES), "flags": flags,
             "parallelism": "single GPU",
         },
         "roofline": roof,
