@@ -70,7 +70,11 @@ enum jacobi_flags {
     JACOBI_FLAG_EXPLICIT_HALO = 1,
     /* Store pass outputs with the non-temporal hint (not kept in the caches).
      * A pure performance choice; results are identical either way. */
-    JACOBI_FLAG_NT_STORES = 2
+    JACOBI_FLAG_NT_STORES = 2,
+    /* 2D passes load rows three steps ahead of their use instead of one
+     * (more bytes in flight per wave, more registers per wave).  A pure
+     * performance choice; results are identical either way. */
+    JACOBI_FLAG_DEEP_PREFETCH = 4
 };
 
 /* ---------------------------------------------------------------- set-up */

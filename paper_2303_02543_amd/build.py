@@ -20,6 +20,12 @@ ARCH = "gfx950"
 
 SOURCES = ["jacobi_abi.hip", "k_layout.hip", "k_sweep.hip", "k_march2d.hip", "k_march3d.hip",
            "k_residual.hip", "k_batch.hip"]
+# k_march2d.hip is compiled once per temporal depth (its kernels) and once
+# more for the depth dispatch; each entry: (source, object name, defines)
+MARCH2D_DEPTHS = range(1, 9)
+UNITS = ([(s, os.path.splitext(s)[0], []) for s in SOURCES] +
+         [("k_march2d.hip", "k_march2d_d%d" % d, ["-DJAC_MARCH2D_DEPTH=%d" % d])
+          for d in MARCH2D_DEPTHS])
 HEADERS = ["jacobi_internal.h", "kernels.h", "device_util.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -30,10 +36,11 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
-def _compile(src, verbose):
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-c",
-                             os.path.join(CSRC, src), "-o", obj]
+def _compile(unit, verbose):
+    src, name, defines = unit
+    obj = os.path.join(BUILD_DIR, name + ".o")
+    cmd = [HIPCC] + FLAGS + defines + ["-I", os.path.join(ROOT, "include"), "-c",
+                                       os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -46,7 +53,10 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     """Compile every HIP source for gfx950 and link libjacobi.so.  Always rebuilds."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        # the largest units first, so they do not end up last in the queue
+        units = sorted(UNITS, key=lambda u: -int(u[1].rsplit("_d", 1)[-1])
+                       if u[1].startswith("k_march2d_d") else 0)
+        objs = list(ex.map(lambda u: _compile(u, verbose), units))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

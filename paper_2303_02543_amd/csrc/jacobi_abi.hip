@@ -68,7 +68,10 @@ int plan(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, Geom *
     const size_t es = dtype == JACOBI_F32 ? 4 : 8;
     std::memset(g, 0, sizeof *g);
     g->ndim = ndim;
-    g->ax = (int)(32 / es);
+    // x extents are multiples of 32 bytes (every 16-byte lane chunk of a row
+    // lies in one block); interior rows start 128 bytes into their row
+    const int xgran = (int)(32 / es);
+    g->ax = (int)(128 / es);
     for (int a = 0; a < 3; ++a) {
         int64_t n = 1, b = 1;
         if (a < ndim) {
@@ -81,7 +84,7 @@ int plan(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, Geom *
                             (long long)b, a, (long long)n);
         }
         int64_t e = (n + b - 1) / b;
-        if (a == 0) e = (e + g->ax - 1) / g->ax * g->ax;
+        if (a == 0) e = (e + xgran - 1) / xgran * xgran;
         if ((b - 1) * e >= n)
             return fail(JACOBI_E_INVAL,
                         "blocks[%d] = %lld leaves the last block empty (block extent %lld, n = %lld)",
@@ -90,12 +93,18 @@ int plan(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, Geom *
         g->nb[a] = (int)b;
         g->e[a] = (int)e;
     }
-    size_t pitch = (size_t)g->e[0] + 2 * (size_t)g->ax, plane, bstride, sstride, nblk, t;
+    // pitch: a multiple of 128 bytes, so every interior row is 128-byte
+    // aligned; the east ring cell of a full-width row may be element 0 of the
+    // next row, which no row uses (west rings sit at ax - 1)
+    size_t pitch = (size_t)g->ax + round_up((size_t)g->e[0], (size_t)g->ax), plane, bstride,
+           sstride, nblk, t;
     if (!mul_ok(pitch, (size_t)g->e[1] + 2, &plane)) return fail(JACOBI_E_INVAL, "size overflow");
     bstride = plane;
     if (ndim == 3 && !mul_ok(plane, (size_t)g->e[2] + 2, &bstride))
         return fail(JACOBI_E_INVAL, "size overflow");
-    bstride = round_up(bstride, 64);
+    // slack after the last row: its east ring and a 16-byte chunk loaded
+    // from there stay inside the block
+    bstride = round_up(bstride + (size_t)g->ax, 64);
     if (!mul_ok((size_t)g->e[0], (size_t)g->e[1], &sstride) ||
         !mul_ok(sstride, (size_t)g->e[2], &sstride))
         return fail(JACOBI_E_INVAL, "size overflow");
@@ -175,15 +184,15 @@ int check_handle(jacobi_t h) {
 
 // Tile height that makes one march launch fill the GPU in `rounds` whole
 // rounds of resident waves: strips x tiles ~= rounds x (waves per CU x CUs).
-int balanced_rows(const jacobi_s *h, int depth, int mode, int rounds) {
+int balanced_rows(const jacobi_s *h, int depth, int mode, int rounds, int deep) {
     if (h->g.ndim != 2) return 64;
     int cus = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
         return 64;
-    const int wpc = h->dtype == JACOBI_F32 ? jac::march2d_waves_per_cu<float>(depth, mode)
-                                           : jac::march2d_waves_per_cu<double>(depth, mode);
+    const int wpc = h->dtype == JACOBI_F32 ? jac::march2d_waves_per_cu<float>(depth, mode, deep)
+                                           : jac::march2d_waves_per_cu<double>(depth, mode, deep);
     const int64_t strips = h->dtype == JACOBI_F32 ? jac::march2d_strips<float>(h->g, depth)
                                                   : jac::march2d_strips<double>(h->g, depth);
     if (wpc <= 0 || strips <= 0) return 64;
@@ -203,9 +212,20 @@ int default_depth(const jacobi_s *h) {
     return h->dtype == JACOBI_F32 ? 8 : 4;
 }
 
+// The 2D pass kernels address a lane's chunk as a 32-bit byte offset from a
+// row of block column 0; grids whose block columns span 4 GiB or more use
+// the explicit-halo sweep and the standalone residual kernel instead.
+bool march_fits(const Geom &g, int dtype) {
+    const double es = dtype == JACOBI_F32 ? 4.0 : 8.0;
+    const double span = (double)g.nb[0] * (double)(g.bstride > g.sstride ? g.bstride : g.sstride);
+    return span * es < 4294967296.0 - 4096.0;
+}
+
+int deep_of(const jacobi_s *h) { return (h->flags & JACOBI_FLAG_DEEP_PREFETCH) ? 1 : 0; }
+
 int default_rows(const jacobi_s *h) {
     const int d = h->depth > 0 ? h->depth : default_depth(h);
-    return balanced_rows(h, d, h->has_source ? 1 : 0, 1);
+    return balanced_rows(h, d, h->has_source ? 1 : 0, 1, deep_of(h));
 }
 
 int max_depth(int ndim, int dtype) {
@@ -269,14 +289,14 @@ int do_residual(jacobi_t h, double *out) {
                 "residual launch");
         return JACOBI_OK;
     }
-    if (h->g.ndim == 2) {
+    if (h->g.ndim == 2 && march_fits(h->g, h->dtype)) {
         // one residual-only pass of the march kernel (no stores)
-        const int rows = balanced_rows(h, 1, h->has_source ? 1 : 0, 1);
+        const int rows = balanced_rows(h, 1, h->has_source ? 1 : 0, 1, deep_of(h));
         const int64_t nw = jac::march2d_work_items<R>(h->g, 1, rows);
         if (nw < 0 || (size_t)nw > h->lay.part_cap) return fail(JACOBI_E_INVAL, "partials overflow");
         int64_t nwork = 0;
         HIP_TRY(jac::launch_sweep2d_march<R>(h->g, h->u[h->cur], nullptr, b, h->partials, nullptr, 1, rows,
-                                             h->stream, &nwork),
+                                             h->stream, &nwork, 0, deep_of(h)),
                 "residual launch");
         HIP_TRY(jac::launch_residual_final(h->partials, (int)nwork, out, h->stream),
                 "residual launch");
@@ -292,7 +312,8 @@ int do_residual(jacobi_t h, double *out) {
 template <typename R>
 int do_sweep(jacobi_t h, int64_t n, double *res_first) {
     const void *b = h->has_source ? h->b : nullptr;
-    const bool explicit_halo = (h->flags & JACOBI_FLAG_EXPLICIT_HALO) != 0;
+    const bool explicit_halo = (h->flags & JACOBI_FLAG_EXPLICIT_HALO) != 0 ||
+                               (h->g.ndim == 2 && !march_fits(h->g, h->dtype));
     if (h->g.ndim == 3 && !explicit_halo && n > 0) {
         // fused 3D passes, one sweep each; the first also sums the residual
         const int zseg = zseg_of(h);
@@ -355,7 +376,7 @@ int do_sweep(jacobi_t h, int64_t n, double *res_first) {
         int64_t nwork = 0;
         HIP_TRY(jac::launch_sweep2d_march<R>(h->g, h->u[h->cur], h->u[h->cur ^ 1], b, part, nullptr, t,
                                              rows, h->stream, &nwork,
-                                             h->flags & JACOBI_FLAG_NT_STORES),
+                                             h->flags & JACOBI_FLAG_NT_STORES, deep_of(h)),
                 "sweep launch");
         rc = prof_end(h, t);
         if (rc) return rc;
@@ -374,7 +395,7 @@ int do_sweep(jacobi_t h, int64_t n, double *res_first) {
 template <typename R>
 int do_adjoint(jacobi_t h, int64_t n) {
     int depth = h->adj_depth > 0 ? h->adj_depth : (h->dtype == JACOBI_F32 ? 4 : 3);
-    const int rows = h->adj_rows > 0 ? h->adj_rows : balanced_rows(h, depth, 2, 1);
+    const int rows = h->adj_rows > 0 ? h->adj_rows : balanced_rows(h, depth, 2, 1, 0);
     int64_t left = n;
     while (left > 0) {
         const int64_t passes = (left + depth - 1) / depth;
@@ -592,6 +613,9 @@ int jacobi_adjoint_begin(jacobi_t h, const void *lam, double *grad_b) {
     if (rc) return rc;
     if (!lam || !grad_b) return fail(JACOBI_E_INVAL, "lam and grad_b must not be NULL");
     if (h->g.ndim != 2) return fail(JACOBI_E_UNSUPPORTED, "the adjoint is implemented for 2D grids");
+    if (!march_fits(h->g, h->dtype))
+        return fail(JACOBI_E_UNSUPPORTED,
+                    "the adjoint pass needs the grid's block columns to span less than 4 GiB");
     if (h->dtype == JACOBI_F32) {
         HIP_TRY(jac::launch_scatter<float>(h->g, lam, h->u[0], h->u[1], true, h->stream),
                 "scatter launch");
@@ -640,7 +664,7 @@ int jacobi_set_tuning(jacobi_t h, int t_depth, int rows, int flags) {
         return fail(JACOBI_E_INVAL, "t_depth must be in [0, %d] (got %d)", md, t_depth);
     if (rows < 0 || (rows > 0 && rows < kMinRows) || rows > (1 << 20))
         return fail(JACOBI_E_INVAL, "rows must be 0 or in [%d, 2^20] (got %d)", kMinRows, rows);
-    if (flags & ~(JACOBI_FLAG_EXPLICIT_HALO | JACOBI_FLAG_NT_STORES))
+    if (flags & ~(JACOBI_FLAG_EXPLICIT_HALO | JACOBI_FLAG_NT_STORES | JACOBI_FLAG_DEEP_PREFETCH))
         return fail(JACOBI_E_INVAL, "unknown flags 0x%x", flags);
     h->depth = t_depth;
     h->rows = rows;
@@ -764,19 +788,21 @@ int jacobi_autotune(jacobi_t h, int64_t n_sweeps, int with_source, int *t_depth,
             const int *list;
             const int nd = jac::march2d_depths(h->dtype, &list);
             static const int kRows[] = {16, 32, 64, 96, 128, 192, 256};
-            for (int i = 0; i < nd; ++i) {
-                std::vector<int> rs(kRows, kRows + sizeof(kRows) / sizeof(int));
-                for (int k = 1; k <= 3; ++k) rs.push_back(balanced_rows(h, list[i], src, k));
-                std::vector<int> seen;
-                for (int r : rs) {
-                    bool dup = false;
-                    for (int q : seen) dup = dup || q == r;
-                    if (dup) continue;
-                    seen.push_back(r);
-                    cands.push_back({list[i], r, 0});
-                    cands.push_back({list[i], r, (int)JACOBI_FLAG_NT_STORES});
+            for (int i = 0; i < nd; ++i)
+                for (int deep = 0; deep <= 1; ++deep) {
+                    std::vector<int> rs(kRows, kRows + sizeof(kRows) / sizeof(int));
+                    for (int k = 1; k <= 3; ++k) rs.push_back(balanced_rows(h, list[i], src, k, deep));
+                    std::vector<int> seen;
+                    const int fd = deep ? (int)JACOBI_FLAG_DEEP_PREFETCH : 0;
+                    for (int r : rs) {
+                        bool dup = false;
+                        for (int q : seen) dup = dup || q == r;
+                        if (dup) continue;
+                        seen.push_back(r);
+                        cands.push_back({list[i], r, fd});
+                        cands.push_back({list[i], r, fd | (int)JACOBI_FLAG_NT_STORES});
+                    }
                 }
-            }
         }
         const bool saved_src = h->has_source;
         const bool saved_prof = h->profiling;
@@ -883,6 +909,8 @@ int batch_plan(int count, const int64_t *grids, int64_t block, int dtype, BatchL
             }
         }
         if (rc != JACOBI_OK) return rc;
+        if (!march_fits(bl->geoms[i], dtype))
+            return fail(JACOBI_E_INVAL, "grid %d: block columns span 4 GiB or more", i);
         bl->base[i] = off;
         // a grid needs its two state buffers and its source (not the
         // single-grid partials/scratch area)

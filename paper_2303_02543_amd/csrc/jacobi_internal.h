@@ -4,15 +4,19 @@
 //   The interior is cut into nb[0] x nb[1] (x nb[2]) blocks with maximum
 //   extents e[0], e[1] (, e[2]); block (p, q, r) owns interior nodes
 //   p*e[0] ... min((p+1)*e[0], n[0]) - 1 along x, and likewise on y and z.
-//   e[0] is a multiple of AX = 32 bytes of elements, so every 16-byte lane
-//   chunk of a row lies inside one block.
+//   e[0] is a multiple of 32 bytes of elements, so every 16-byte lane chunk
+//   of a row lies inside one block.
 //   Each block stores its interior plus a one-cell halo ring as rows of
-//   `pitch` = e[0] + 2*AX elements: local node (lx, ly, lz) with
-//   lx in [-1, ex], ly in [-1, ey], lz in [-1, ez] lives at element
+//   `pitch` = AX + e[0] rounded up to AX elements, AX = 128 bytes of
+//   elements: local node (lx, ly, lz) with lx in [-1, ex], ly in [-1, ey],
+//   lz in [-1, ez] lives at element
 //       blk * bstride + (lz+1) * plane + (ly+1) * pitch + AX + lx
-//   with plane = (e[1]+2) * pitch (the plane term is absent in 2D)
-//   so interior rows start 32-byte aligned and a whole block is one
-//   contiguous stream of rows.  Halo cells on the domain boundary hold the
+//   with plane = (e[1]+2) * pitch (the plane term is absent in 2D), so every
+//   interior row starts 128-byte aligned (an interior row of 2^k cache lines
+//   is fetched as exactly those lines) and a whole block is one contiguous
+//   stream of rows.  The east ring cell (lx = ex) of a full-width row is
+//   element 0 of the next row, a slot no row uses; bstride leaves AX
+//   elements of slack after the last row.  Halo cells on the domain boundary hold the
 //   Dirichlet ring; the others mirror the face neighbour's edge cells.
 //   Source b is stored per block without halo: element
 //       blk * sstride + (lz * e[1] + ly) * e[0] + lx.
@@ -26,7 +30,7 @@ constexpr int kMaxDim = 3;
 
 struct Geom {
     int ndim;
-    int ax;              // x alignment in elements (32 bytes)
+    int ax;              // offset of interior column 0 in a row, elements (128 bytes)
     int n[3];            // interior nodes per axis (x, y, z); 1 for unused axes
     int nb[3];           // blocks per axis
     int e[3];            // maximum block extent per axis

@@ -18,10 +18,18 @@
 // A strip recomputes T - 1 columns on each side and a segment T rows on each
 // side; only the strip's output lanes [L0, L1) and the segment's own rows
 // are stored.  Rows are loaded one step ahead of use, straight into their
-// ring slot, so no register copies are needed.
+// ring slot, so no register copies are needed.  A source row waits in
+// registers for one step before it is written to the wave's LDS ring (it is
+// first read one step after that), so the wait for its load overlaps a whole
+// step of arithmetic instead of stalling the step that issued it.
 //
-// Strips that touch the Dirichlet ring (first/last strip) run a second copy
-// of the body with per-element masks; every other strip is branch-free.
+// Every load is unconditional: a load issued on only some paths would turn
+// the next step's wait for its data into a wait for every load in flight.
+// Tiles that reach the Dirichlet ring or the rows beyond it (first/last
+// strip, first/last row segment) run an edge copy of the body, which reads an
+// in-bounds stand-in address where a row or column lies outside the grid,
+// zeroes what it read there, and keeps ring cells at their values.  Interior
+// tiles run a copy with no row or column tests at all.
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
@@ -35,7 +43,7 @@ namespace jac {
 // into an FP64 accumulator.
 enum { MODE_LAPLACE = 0, MODE_POISSON = 1, MODE_ADJOINT = 2 };
 
-template <typename R, int T>
+template <typename R, int T, int P>
 struct M2 {
     static constexpr int V = 16 / (int)sizeof(R);            // elements per lane
     static constexpr int W = 64 * V;                          // strip width
@@ -43,8 +51,17 @@ struct M2 {
     static constexpr int OW = V * ((W - (T - 1) - A0) / V);   // output columns per strip
     static constexpr int L0 = A0 / V;                         // first output lane
     static constexpr int L1 = (A0 + OW) / V;                  // one past the last output lane
+    // rows loaded ahead (prefetch distance): row r + P is loaded at step r
+    static_assert(P >= 1 && P <= 3, "prefetch distance 1..3");
+    static constexpr int LR = P == 1 ? 4 : 6;                 // level-0 ring: rows r-2 .. r+P
+    static constexpr int BQ = P == 1 ? 2 : P;                 // source registers: rows r .. r+P
+    // BQ == P: the slot of row r is reused for row r + P, so row r goes to
+    // LDS before that load is issued; otherwise after it
+    static constexpr bool WRITE_FIRST = BQ == P;
     static constexpr int U = 12;                              // steps per unrolled group
-    static constexpr int RB = T + 2;                          // source rows r-T .. r+1 (LDS)
+    // ring slots are compile-time step indices mod 4, 3 and 2
+    static_assert(U % LR == 0 && U % 3 == 0 && U % BQ == 0, "ring sizes must divide U");
+    static constexpr int RB = T + 1;                          // source rows r-T .. r (LDS)
     static constexpr int NL = T > 1 ? T - 1 : 1;              // stored levels 1..T-1
     // adjoint accumulator rows r-T+1 .. r+1
     static constexpr int RA = T + 1 <= 2 ? 2 : T + 1 <= 3 ? 3 : T + 1 <= 4 ? 4 : T + 1 <= 6 ? 6 : 12;
@@ -85,11 +102,12 @@ struct Cur {
     }
 };
 
-template <typename R, int T>
+template <typename R, int T, int P>
 struct MRegs {
-    using S = M2<R, T>;
-    R l0[4][S::V];           // level-0 rows, slot = row mod 4 (r-2 .. r+1)
-    R e0[4];                 // level-0 cell just outside the strip (lanes 0, 63)
+    using S = M2<R, T, P>;
+    R l0[S::LR][S::V];       // level-0 rows, slot = row mod LR (r-2 .. r+P)
+    R e0[S::LR];             // level-0 cell just outside the strip (lanes 0, 63)
+    R bq[S::BQ][S::V];       // source rows in flight, slot = row mod BQ
     R lv[S::NL][3][S::V];    // levels 1..T-1, slot = step mod 3
     double ga[S::RA][S::V];  // adjoint: FP64 accumulator rows r-T+1 .. r+1
     double acc;              // residual partial sum (level 1)
@@ -107,14 +125,14 @@ struct MLane {
     int oy0, oy1, r1;
 };
 
-// Issue the loads of row lc.y into level-0 slot SL, source slot SB and (adjoint
-// pass) accumulator slot SA, then advance the cursor.
-template <typename R, int T, int MODE, bool RINGX, int SL, int SA>
+// Issue the loads of row lc.y into level-0 slot SL, source register slot SQ
+// and (adjoint pass) accumulator slot SA, then advance the cursor.
+template <typename R, int T, int P, int MODE, bool EDGE, int SL, int SQ, int SA>
 __device__ __forceinline__ void m2_load(const Geom &g, const R *__restrict__ uin,
                                         const R *__restrict__ bsrc,
                                         const double *__restrict__ gacc, const MLane &L,
-                                        MRegs<R, T> &m, Cur &lc, const int bslot) {
-    constexpr int V = M2<R, T>::V;
+                                        MRegs<R, T, P> &m, Cur &lc) {
+    constexpr int V = M2<R, T, P>::V;
     constexpr bool SRC = MODE == MODE_POISSON;
     using C = Chunk<R, V>;
     const int y = lc.y, ny = g.n[1];
@@ -128,31 +146,20 @@ __device__ __forceinline__ void m2_load(const Geom &g, const R *__restrict__ uin
             m.ga[SA][v] = in ? gacc[(int64_t)y * nx + (L.c + v)] : 0.0;
         }
     }
-    if (y >= -1 && y <= ny) {
-        const R *row = uin + lc.su;
-        if (!RINGX || L.ld) {
-            const C c = at<C>(row, L.lane_b);
+    const bool row_ok = !EDGE || (y >= -1 && y <= ny);
+    const R *row = uin + (row_ok ? lc.su : (int64_t)g.pitch);
+    const C c = at<C>(row, L.lane_b);
+    const R e = at<R>(row, L.edge_b);
+    const bool ok = !EDGE || (row_ok && L.ld);
 #pragma unroll
-            for (int v = 0; v < V; ++v) m.l0[SL][v] = c.v[v];
-        } else {
+    for (int v = 0; v < V; ++v) m.l0[SL][v] = ok ? c.v[v] : (R)0;
+    m.e0[SL] = (!EDGE || (row_ok && L.lde)) ? e : (R)0;
+    if constexpr (SRC) {
+        const bool brow = !EDGE || (y >= 0 && y < ny);
+        const C cb = at<C>(bsrc + (brow ? lc.sb : (int64_t)0), L.src_b);
+        const bool okb = !EDGE || (brow && L.ldb);
 #pragma unroll
-            for (int v = 0; v < V; ++v) m.l0[SL][v] = (R)0;
-        }
-        m.e0[SL] = (!RINGX || L.lde) ? at<R>(row, L.edge_b) : (R)0;
-        if constexpr (SRC) {
-            C c;
-            if (y >= 0 && y < ny && (!RINGX || L.ldb)) {
-                c = at<C>(bsrc + lc.sb, L.src_b);
-            } else {
-#pragma unroll
-                for (int v = 0; v < V; ++v) c.v[v] = (R)0;
-            }
-            static_cast<C *>(L.bs)[bslot * 64] = c;
-        }
-    } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) m.l0[SL][v] = (R)0;
-        m.e0[SL] = (R)0;
+        for (int v = 0; v < V; ++v) m.bq[SQ][v] = okb ? cb.v[v] : (R)0;
     }
     lc.advance(g);
 }
@@ -160,13 +167,13 @@ __device__ __forceinline__ void m2_load(const Geom &g, const R *__restrict__ uin
 // Adjoint pass: add w * (level values of row y) into the row's accumulator,
 // in the order of decreasing sweep index; store the accumulator when its last
 // level (T - 1) has been added.
-template <typename R, int T, int MODE, bool RINGX, int SA, bool LAST>
+template <typename R, int T, int P, int MODE, bool EDGE, int SA, bool LAST>
 __device__ __forceinline__ void m2_accumulate(const Geom &g, double *__restrict__ gacc,
-                                              const MLane &L, MRegs<R, T> &m, const int y,
-                                              const R (&val)[M2<R, T>::V]) {
-    constexpr int V = M2<R, T>::V;
+                                              const MLane &L, MRegs<R, T, P> &m, const int y,
+                                              const R (&val)[M2<R, T, P>::V]) {
+    constexpr int V = M2<R, T, P>::V;
     if constexpr (MODE == MODE_ADJOINT) {
-        if (y >= 0 && y < g.n[1]) {
+        if (!EDGE || (y >= 0 && y < g.n[1])) {
             const R w = (R)0.25;
 #pragma unroll
             for (int v = 0; v < V; ++v) m.ga[SA][v] += (double)(w * val[v]);
@@ -174,7 +181,7 @@ __device__ __forceinline__ void m2_accumulate(const Geom &g, double *__restrict_
                 double *row = gacc + (int64_t)y * g.n[0] + L.c;
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    const bool mine = RINGX ? L.st[v] : L.out_lane;
+                    const bool mine = EDGE ? L.st[v] : L.out_lane;
                     if (mine) row[v] = m.ga[SA][v];
                 }
             }
@@ -185,12 +192,11 @@ __device__ __forceinline__ void m2_accumulate(const Geom &g, double *__restrict_
 // Level S of step J (row r = base + J): computes row r - S from the three
 // newest rows of level S - 1 (level 0 = the loaded rows).  All ring slots are
 // compile-time constants so the rings live in registers.
-template <typename R, int T, int MODE, bool RINGX, int J, int S>
+template <typename R, int T, int P, int MODE, bool EDGE, bool RES, int J, int S>
 __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
-                                         double *__restrict__ gacc, const bool res,
-                                         const MLane &L, MRegs<R, T> &m, const int r,
+                                         double *__restrict__ gacc, const MLane &L, MRegs<R, T, P> &m, const int r,
                                          const Cur &sc, const int sr) {
-    using M = M2<R, T>;
+    using M = M2<R, T, P>;
     constexpr int V = M::V;
     constexpr bool SRC = MODE == MODE_POISSON;
     if constexpr (S <= T) {
@@ -202,9 +208,9 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             if constexpr (S == 1) {
-                up[v] = m.l0[(J + 2) % 4][v];   // row r-2
-                cen[v] = m.l0[(J + 3) % 4][v];  // row r-1
-                dn[v] = m.l0[J % 4][v];         // row r
+                up[v] = m.l0[(J + M::LR - 2) % M::LR][v];   // row r-2
+                cen[v] = m.l0[(J + M::LR - 1) % M::LR][v];  // row r-1
+                dn[v] = m.l0[J % M::LR][v];                 // row r
             } else {
                 up[v] = m.lv[S - 2][(J + 1) % 3][v];
                 cen[v] = m.lv[S - 2][(J + 2) % 3][v];
@@ -219,13 +225,13 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
             for (int v = 0; v < V; ++v) bv[v] = c.v[v];
         }
         R out[V];
-        if (y >= 0 && y < ny) {
+        if (!EDGE || (y >= 0 && y < ny)) {
             R eo = (R)0;
-            if constexpr (S == 1) eo = m.e0[(J + 3) % 4];
+            if constexpr (S == 1) eo = m.e0[(J + M::LR - 1) % M::LR];
             const R left = shift_up(eo, cen[V - 1]);
             const R right = shift_down(eo, cen[0]);
             const R w = (R)0.25;
-            const bool acc_row = (S == 1) && res && y >= L.oy0 && y < L.oy1;
+            const bool acc_row = (S == 1) && RES && y >= L.oy0 && y < L.oy1;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const R Wv = v > 0 ? cen[v - 1] : left;
@@ -243,12 +249,12 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
                             ((double)Wv + (double)Ev) + ((double)up[v] + (double)dn[v]);
                         const double bd = SRC ? (double)bv[v] : 0.0;
                         const double rr = bd - (4.0 * (double)cen[v] - sd);
-                        const bool mine = RINGX ? L.st[v] : L.out_lane;
+                        const bool mine = EDGE ? L.st[v] : L.out_lane;
                         m.acc += mine ? rr * rr : 0.0;
                     }
                 }
                 // ring cells (and cells beyond the ring) keep their values
-                if constexpr (RINGX) o = L.upd[v] ? o : cen[v];
+                if constexpr (EDGE) o = L.upd[v] ? o : cen[v];
                 out[v] = o;
             }
         } else {
@@ -258,12 +264,12 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
         if constexpr (S < T) {
 #pragma unroll
             for (int v = 0; v < V; ++v) m.lv[S - 1][J % 3][v] = out[v];
-            m2_accumulate<R, T, MODE, RINGX, (J - S + 2 * M::RA) % M::RA, S == T - 1>(g, gacc, L,
+            m2_accumulate<R, T, P, MODE, EDGE, (J - S + 2 * M::RA) % M::RA, S == T - 1>(g, gacc, L,
                                                                                      m, y, out);
         } else {
             if (uout && y >= L.oy0 && y < L.oy1) {
                 R *row = uout + sc.su;
-                if constexpr (!RINGX) {
+                if constexpr (!EDGE) {
                     if (L.out_lane) {
                         Chunk<R, V> o;
 #pragma unroll
@@ -280,50 +286,61 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
                 }
             }
         }
-        m2_level<R, T, MODE, RINGX, J, S + 1>(g, uout, gacc, res, L, m, r, sc, sr);
+        m2_level<R, T, P, MODE, EDGE, RES, J, S + 1>(g, uout, gacc, L, m, r, sc, sr);
     }
 }
 
-template <typename R, int T, int MODE, bool RINGX, int J>
+template <typename R, int T, int P, int MODE, bool EDGE, bool RES, int J>
 __device__ __forceinline__ void m2_steps(const Geom &g, const R *__restrict__ uin,
                                          R *__restrict__ uout, const R *__restrict__ bsrc,
-                                         double *__restrict__ gacc, const bool res,
-                                         const MLane &L, MRegs<R, T> &m, const int base, Cur &lc,
+                                         double *__restrict__ gacc, const MLane &L, MRegs<R, T, P> &m, const int base, Cur &lc,
                                          Cur &sc, int &sr) {
-    using M = M2<R, T>;
+    using M = M2<R, T, P>;
     constexpr int V = M::V;
     if constexpr (J < M::U) {
         const int r = base + J;
         if (r > L.r1) return;
-        // row r+1 goes into the slots rows r-3 (state), r+1-RB (source) and
-        // r+1-RA (accumulator) held
-        const int sr1 = sr + 1 == M::RB ? 0 : sr + 1;  // LDS source slot of row r+1
-        if (r + 1 <= L.r1)
-            m2_load<R, T, MODE, RINGX, (J + 1) % 4, (J + 1) % M::RA>(g, uin, bsrc, gacc, L, m, lc,
-                                                                     sr1);
+        // the source row r, loaded P steps ago, moves to the LDS slot that
+        // row r - RB held; levels read it from the next step on
+        auto to_lds = [&]() {
+            if constexpr (MODE == MODE_POISSON) {
+                Chunk<R, V> c;
+#pragma unroll
+                for (int v = 0; v < V; ++v) c.v[v] = m.bq[J % M::BQ][v];
+                static_cast<Chunk<R, V> *>(L.bs)[sr * 64] = c;
+            }
+        };
+        if constexpr (M::WRITE_FIRST) to_lds();
+        // row r+P goes into the slots rows r+P-LR (state), r+P-BQ (source
+        // registers) and r+1-RA (accumulator, P = 1) held; at the last P
+        // steps this reads rows no level uses, which keeps the loads
+        // unconditional
+        m2_load<R, T, P, MODE, EDGE, (J + P) % M::LR, (J + P) % M::BQ, (J + 1) % M::RA>(
+            g, uin, bsrc, gacc, L, m, lc);
+        if constexpr (!M::WRITE_FIRST) to_lds();
         if constexpr (MODE == MODE_ADJOINT) {
             // level 0 of row r (the pass's input) is the first term added
             R v0[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) v0[v] = m.l0[J % 4][v];
-            m2_accumulate<R, T, MODE, RINGX, J % M::RA, T == 1>(g, gacc, L, m, r, v0);
+            for (int v = 0; v < V; ++v) v0[v] = m.l0[J % M::LR][v];
+            m2_accumulate<R, T, P, MODE, EDGE, J % M::RA, T == 1>(g, gacc, L, m, r, v0);
         }
-        m2_level<R, T, MODE, RINGX, J, 1>(g, uout, gacc, res, L, m, r, sc, sr);
+        m2_level<R, T, P, MODE, EDGE, RES, J, 1>(g, uout, gacc, L, m, r, sc, sr);
         sc.advance(g);
-        sr = sr1;
-        m2_steps<R, T, MODE, RINGX, J + 1>(g, uin, uout, bsrc, gacc, res, L, m, base, lc, sc, sr);
+        sr = sr + 1 == M::RB ? 0 : sr + 1;
+        m2_steps<R, T, P, MODE, EDGE, RES, J + 1>(g, uin, uout, bsrc, gacc, L, m, base, lc, sc, sr);
     }
 }
 
-template <typename R, int T, int MODE, bool RINGX>
+template <typename R, int T, int P, int MODE, bool EDGE, bool RES>
 __device__ __forceinline__ void m2_body(const Geom &g, const R *__restrict__ uin,
                                         R *__restrict__ uout, const R *__restrict__ bsrc,
                                         double *__restrict__ res_slot,
                                         double *__restrict__ gacc, const MLane &L, int r0) {
-    using S = M2<R, T>;
-    MRegs<R, T> m;
+    using S = M2<R, T, P>;
+    MRegs<R, T, P> m;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < S::LR; ++k) {
         m.e0[k] = (R)0;
 #pragma unroll
         for (int v = 0; v < S::V; ++v) m.l0[k][v] = (R)0;
@@ -342,27 +359,29 @@ __device__ __forceinline__ void m2_body(const Geom &g, const R *__restrict__ uin
     Cur lc, sc;
     lc.init(g, r0);
     sc.init(g, r0 - T);
-    m2_load<R, T, MODE, RINGX, 0, 0>(g, uin, bsrc, gacc, L, m, lc, 0);  // row r0 -> slot 0
-    const bool want_res = res_slot != nullptr;
+    // rows r0 .. r0+P-1 -> slots 0 .. P-1
+    m2_load<R, T, P, MODE, EDGE, 0, 0, 0>(g, uin, bsrc, gacc, L, m, lc);
+    if constexpr (P > 1) m2_load<R, T, P, MODE, EDGE, 1, 1 % S::BQ, 1 % S::RA>(g, uin, bsrc, gacc, L, m, lc);
+    if constexpr (P > 2) m2_load<R, T, P, MODE, EDGE, 2, 2 % S::BQ, 2 % S::RA>(g, uin, bsrc, gacc, L, m, lc);
     int sr = 0;  // LDS source slot of the current row
     for (int base = r0; base <= L.r1; base += S::U)
-        m2_steps<R, T, MODE, RINGX, 0>(g, uin, uout, bsrc, gacc, want_res, L, m, base, lc, sc, sr);
-    if (want_res) {
+        m2_steps<R, T, P, MODE, EDGE, RES, 0>(g, uin, uout, bsrc, gacc, L, m, base, lc, sc, sr);
+    if constexpr (RES) {
         const double a = wave_sum(m.acc);
         if ((threadIdx.x & 63) == 0) *res_slot = a;
     }
 }
 
 // One work item (wave): strip/tile number `wid` of a grid with `nseg` tiles
-// per strip.  wid is wave-uniform.  res_slot: where the wave's residual
-// partial goes (NULL: none).  bs_wave: the wave's LDS source ring.
-template <typename R, int T, int MODE>
+// per strip.  wid is wave-uniform.  RES: accumulate the residual partial into
+// *res_slot.  bs_wave: the wave's LDS source ring.
+template <typename R, int T, int P, int MODE, bool RES>
 __device__ __forceinline__ void m2_run(const Geom &g, const R *__restrict__ uin,
                                        R *__restrict__ uout, const R *__restrict__ bsrc,
                                        double *__restrict__ res_slot, double *__restrict__ gacc,
-                                       int wid, int nseg, int rows, Chunk<R, M2<R, T>::V> *bs_wave,
+                                       int wid, int nseg, int rows, Chunk<R, M2<R, T, P>::V> *bs_wave,
                                        bool nt) {
-    using S = M2<R, T>;
+    using S = M2<R, T, P>;
     constexpr bool SRC = MODE == MODE_POISSON;
     constexpr int V = S::V;
     const int lane = threadIdx.x & 63;
@@ -401,46 +420,50 @@ __device__ __forceinline__ void m2_run(const Geom &g, const R *__restrict__ uin,
         L.upd[v] = x >= 0 && x < nx;
         L.st[v] = v < V && L.upd[v] && L.out_lane;
     }
-    const bool ringx = a < 0 || a + S::W > nx;
+    // rows r0 .. r1 + P are read; an interior tile reads only grid rows and
+    // columns, none of them on the ring
+    static_assert(MODE != MODE_ADJOINT || P == 1, "the adjoint pass prefetches one row");
     const int r0 = L.oy0 - T;
-    if (ringx)
-        m2_body<R, T, MODE, true>(g, uin, uout, bsrc, res_slot, gacc, L, r0);
+    const bool edge = a < 0 || a + S::W > nx || r0 < 0 || L.r1 + P > ny - 1;
+    if (edge)
+        m2_body<R, T, P, MODE, true, RES>(g, uin, uout, bsrc, res_slot, gacc, L, r0);
     else
-        m2_body<R, T, MODE, false>(g, uin, uout, bsrc, res_slot, gacc, L, r0);
+        m2_body<R, T, P, MODE, false, RES>(g, uin, uout, bsrc, res_slot, gacc, L, r0);
 }
 
-// uout may be NULL (no stores: residual only); res may be NULL (no residual);
-// gacc is the FP64 accumulator of the adjoint pass (MODE_ADJOINT only).
-template <typename R, int T, int MODE>
+// uout may be NULL (no stores: residual only); res (used when RES) receives
+// one residual partial per work item; gacc is the FP64 accumulator of the
+// adjoint pass (MODE_ADJOINT only).
+template <typename R, int T, int P, int MODE, bool RES>
 __global__ __launch_bounds__(256) void k_march2d(Geom g, const R *__restrict__ uin,
                                                  R *__restrict__ uout,
                                                  const R *__restrict__ bsrc,
                                                  double *__restrict__ res,
                                                  double *__restrict__ gacc, int nseg, int rows,
                                                  int nwork, int nt) {
-    using S = M2<R, T>;
+    using S = M2<R, T, P>;
     constexpr bool SRC = MODE == MODE_POISSON;
     // per wave: a ring of RB source rows, one 16-byte chunk per lane each
     __shared__ Chunk<R, S::V> bsm[SRC ? 4 * S::RB * 64 : 1];
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int wid = __builtin_amdgcn_readfirstlane(lb * (blockDim.x >> 6) + (threadIdx.x >> 6));
     if (wid >= nwork) return;
-    m2_run<R, T, MODE>(g, uin, uout, bsrc, res ? res + wid : nullptr, gacc, wid, nseg, rows,
-                       &bsm[SRC ? (threadIdx.x >> 6) * S::RB * 64 : 0], nt != 0);
+    m2_run<R, T, P, MODE, RES>(g, uin, uout, bsrc, RES ? res + wid : nullptr, gacc, wid, nseg,
+                               rows, &bsm[SRC ? (threadIdx.x >> 6) * S::RB * 64 : 0], nt != 0);
 }
 
 // Batched pass: the work items of all grids of a batch in one launch.  Work
 // item w belongs to grid gi with prefix[gi] <= w < prefix[gi+1]; inactive
 // grids (stopped by the convergence test) skip their items.  All active
 // grids advance together, so the input buffer is u[pass_count & 1].
-template <typename R, int T>
+template <typename R, int T, int P, bool RES>
 __global__ __launch_bounds__(256) void k_march2d_batch(const BatchGrid *__restrict__ grids,
                                                        const int *__restrict__ prefix, int ngrids,
                                                        const int *__restrict__ active,
                                                        const int *__restrict__ pass_count,
                                                        double *__restrict__ res, int store,
                                                        int rows, int nwork) {
-    using S = M2<R, T>;
+    using S = M2<R, T, P>;
     __shared__ Chunk<R, S::V> bsm[4 * S::RB * 64];
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int wid = __builtin_amdgcn_readfirstlane(lb * (blockDim.x >> 6) + (threadIdx.x >> 6));
@@ -456,43 +479,140 @@ __global__ __launch_bounds__(256) void k_march2d_batch(const BatchGrid *__restri
     const int par = *pass_count & 1;
     const R *uin = (const R *)grids[gi].u[par];
     R *uout = store ? (R *)grids[gi].u[par ^ 1] : nullptr;
-    m2_run<R, T, MODE_POISSON>(g, uin, uout, (const R *)grids[gi].b, res ? res + wid : nullptr,
-                               nullptr, wid - prefix[gi], grids[gi].nseg, rows,
-                               &bsm[(threadIdx.x >> 6) * S::RB * 64], false);
+    m2_run<R, T, P, MODE_POISSON, RES>(g, uin, uout, (const R *)grids[gi].b,
+                                    RES ? res + wid : nullptr, nullptr, wid - prefix[gi],
+                                    grids[gi].nseg, rows, &bsm[(threadIdx.x >> 6) * S::RB * 64],
+                                    false);
 }
+
+// ---- host side -------------------------------------------------------------
+// The kernels of each temporal depth T are compiled in an object of their
+// own (this file built with JAC_MARCH2D_DEPTH=T), so the depths compile in
+// parallel; the object built without it holds the depth dispatch only, which
+// sees the per-depth launchers as declarations and instantiates no kernel.
 
 template <typename R, int T>
 static int64_t m2_nwork(const Geom &g, int rows, int *nseg_out) {
-    using S = M2<R, T>;
+    using S = M2<R, T, 1>;  // the tiling does not depend on the prefetch distance
     const int64_t nstrips = (g.n[0] + S::OW - 1) / S::OW;
     const int64_t nseg = (g.n[1] + rows - 1) / rows;
     if (nseg_out) *nseg_out = (int)nseg;
     return nstrips * nseg;
 }
 
+// deep != 0: the kernels that load three rows ahead (otherwise one)
 template <typename R, int T>
-static hipError_t m2_launch_t(const Geom &g, const void *uin, void *uout, const void *b,
-                              double *res, double *gacc, int rows, hipStream_t st,
-                              int64_t *nwork_out, int nt) {
+hipError_t m2_launch_t(const Geom &g, const void *uin, void *uout, const void *b, double *res,
+                       double *gacc, int rows, hipStream_t st, int64_t *nwork_out, int nt,
+                       int deep);
+template <typename R, int T>
+hipError_t m2b_launch_t(const BatchGrid *grids, const int *prefix, int ngrids, const int *active,
+                        const int *pass_count, double *res, bool store, int rows, int nwork,
+                        hipStream_t st, int deep);
+template <typename R, int T>
+int m2_waves_per_cu_t(int mode, int deep);
+
+#ifdef JAC_MARCH2D_DEPTH
+
+template <typename R, int T, int P>
+static hipError_t m2_launch_p(const Geom &g, const void *uin, void *uout, const void *b,
+                              double *res, double *gacc, int rows, int nseg, int nwork,
+                              hipStream_t st, int nt) {
+    const int grid = (nwork + 3) / 4;
+    const R *bb = (const R *)b;
+    if (gacc)
+        hipLaunchKernelGGL((k_march2d<R, T, 1, MODE_ADJOINT, false>), dim3(grid), dim3(256), 0, st,
+                           g, (const R *)uin, (R *)uout, (const R *)nullptr, (double *)nullptr,
+                           gacc, nseg, rows, nwork, nt);
+    else if (b && res)
+        hipLaunchKernelGGL((k_march2d<R, T, P, MODE_POISSON, true>), dim3(grid), dim3(256), 0, st,
+                           g, (const R *)uin, (R *)uout, bb, res, (double *)nullptr, nseg, rows,
+                           nwork, nt);
+    else if (b)
+        hipLaunchKernelGGL((k_march2d<R, T, P, MODE_POISSON, false>), dim3(grid), dim3(256), 0, st,
+                           g, (const R *)uin, (R *)uout, bb, (double *)nullptr, (double *)nullptr,
+                           nseg, rows, nwork, nt);
+    else if (res)
+        hipLaunchKernelGGL((k_march2d<R, T, P, MODE_LAPLACE, true>), dim3(grid), dim3(256), 0, st,
+                           g, (const R *)uin, (R *)uout, (const R *)nullptr, res,
+                           (double *)nullptr, nseg, rows, nwork, nt);
+    else
+        hipLaunchKernelGGL((k_march2d<R, T, P, MODE_LAPLACE, false>), dim3(grid), dim3(256), 0, st,
+                           g, (const R *)uin, (R *)uout, (const R *)nullptr, (double *)nullptr,
+                           (double *)nullptr, nseg, rows, nwork, nt);
+    return hipGetLastError();
+}
+
+template <typename R, int T>
+hipError_t m2_launch_t(const Geom &g, const void *uin, void *uout, const void *b, double *res,
+                       double *gacc, int rows, hipStream_t st, int64_t *nwork_out, int nt,
+                       int deep) {
     int nseg = 0;
     const int64_t nwork = m2_nwork<R, T>(g, rows, &nseg);
     if (nwork_out) *nwork_out = nwork;
     if (nwork > 0x7fffffff) return hipErrorInvalidValue;
-    const int grid = (int)((nwork + 3) / 4);
-    if (gacc)
-        hipLaunchKernelGGL((k_march2d<R, T, MODE_ADJOINT>), dim3(grid), dim3(256), 0, st, g,
-                           (const R *)uin, (R *)uout, (const R *)nullptr, (double *)nullptr,
-                           gacc, nseg, rows, (int)nwork, nt);
-    else if (b)
-        hipLaunchKernelGGL((k_march2d<R, T, MODE_POISSON>), dim3(grid), dim3(256), 0, st, g,
-                           (const R *)uin, (R *)uout, (const R *)b, res, (double *)nullptr, nseg,
-                           rows, (int)nwork, nt);
+    if (deep && !gacc)
+        return m2_launch_p<R, T, 3>(g, uin, uout, b, res, gacc, rows, nseg, (int)nwork, st, nt);
+    return m2_launch_p<R, T, 1>(g, uin, uout, b, res, gacc, rows, nseg, (int)nwork, st, nt);
+}
+
+template <typename R, int T, int P>
+static hipError_t m2b_launch_p(const BatchGrid *grids, const int *prefix, int ngrids,
+                               const int *active, const int *pass_count, double *res, bool store,
+                               int rows, int nwork, hipStream_t st) {
+    const int grid = (nwork + 3) / 4;
+    if (res)
+        hipLaunchKernelGGL((k_march2d_batch<R, T, P, true>), dim3(grid), dim3(256), 0, st, grids,
+                           prefix, ngrids, active, pass_count, res, store ? 1 : 0, rows, nwork);
     else
-        hipLaunchKernelGGL((k_march2d<R, T, MODE_LAPLACE>), dim3(grid), dim3(256), 0, st, g,
-                           (const R *)uin, (R *)uout, (const R *)nullptr, res, (double *)nullptr,
-                           nseg, rows, (int)nwork, nt);
+        hipLaunchKernelGGL((k_march2d_batch<R, T, P, false>), dim3(grid), dim3(256), 0, st, grids,
+                           prefix, ngrids, active, pass_count, res, store ? 1 : 0, rows, nwork);
     return hipGetLastError();
 }
+
+template <typename R, int T>
+hipError_t m2b_launch_t(const BatchGrid *grids, const int *prefix, int ngrids, const int *active,
+                        const int *pass_count, double *res, bool store, int rows, int nwork,
+                        hipStream_t st, int deep) {
+    if (deep)
+        return m2b_launch_p<R, T, 3>(grids, prefix, ngrids, active, pass_count, res, store, rows,
+                                     nwork, st);
+    return m2b_launch_p<R, T, 1>(grids, prefix, ngrids, active, pass_count, res, store, rows,
+                                 nwork, st);
+}
+
+template <typename R, int T>
+int m2_waves_per_cu_t(int mode, int deep) {
+    int blocks = 0;
+    hipError_t e;
+    if (mode == MODE_ADJOINT)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 1, MODE_ADJOINT, false>, 256, 0);
+    else if (mode == MODE_POISSON && deep)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 3, MODE_POISSON, false>, 256, 0);
+    else if (mode == MODE_POISSON)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 1, MODE_POISSON, false>, 256, 0);
+    else if (deep)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 3, MODE_LAPLACE, false>, 256, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 1, MODE_LAPLACE, false>, 256, 0);
+    return e == hipSuccess ? blocks * 4 : 0;
+}
+
+#define JAC_M2_INSTANTIATE(R, T)                                                              \
+    template hipError_t m2_launch_t<R, T>(const Geom &, const void *, void *, const void *,    \
+                                          double *, double *, int, hipStream_t, int64_t *,     \
+                                          int, int);                                           \
+    template hipError_t m2b_launch_t<R, T>(const BatchGrid *, const int *, int, const int *,   \
+                                           const int *, double *, bool, int, int,              \
+                                           hipStream_t, int);                                  \
+    template int m2_waves_per_cu_t<R, T>(int, int);
+
+JAC_M2_INSTANTIATE(float, JAC_MARCH2D_DEPTH)
+#if JAC_MARCH2D_DEPTH <= 4
+JAC_M2_INSTANTIATE(double, JAC_MARCH2D_DEPTH)
+#endif
+
+#else  // dispatch object
 
 static const int kDepthsF32[] = {1, 2, 3, 4, 5, 6, 7, 8};
 static const int kDepthsF64[] = {1, 2, 3, 4};
@@ -506,144 +626,86 @@ int march2d_depths(int dtype, const int **list) {
     return (int)(sizeof(kDepthsF64) / sizeof(int));
 }
 
-template <typename R>
-int64_t march2d_work_items(const Geom &g, int depth, int rows);
-
-template <typename R, int T>
-static int m2_waves_per_cu_t(int mode) {
-    int blocks = 0;
-    hipError_t e;
-    if (mode == MODE_ADJOINT)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, MODE_ADJOINT>, 256, 0);
-    else if (mode == MODE_POISSON)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, MODE_POISSON>, 256, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, MODE_LAPLACE>, 256, 0);
-    return e == hipSuccess ? blocks * 4 : 0;
-}
-
-template <typename R>
-int march2d_waves_per_cu(int depth, int mode) {
-    switch (depth) {
-    case 1: return m2_waves_per_cu_t<R, 1>(mode);
-    case 2: return m2_waves_per_cu_t<R, 2>(mode);
-    case 3: return m2_waves_per_cu_t<R, 3>(mode);
-    case 4: return m2_waves_per_cu_t<R, 4>(mode);
-    case 5: return m2_waves_per_cu_t<R, 5>(mode);
-    case 6: return m2_waves_per_cu_t<R, 6>(mode);
-    case 7: return m2_waves_per_cu_t<R, 7>(mode);
-    case 8: return m2_waves_per_cu_t<R, 8>(mode);
-    default: return 0;
+// Calls F<R, depth>(args...) for a compiled depth (1..8 in FP32, 1..4 in
+// FP64); `bad` otherwise.
+#define JAC_M2_CASE(F, R, D, BAD, ...)                                  \
+    case D:                                                             \
+        if constexpr (sizeof(R) == 8 && D > 4)                          \
+            return BAD;                                                 \
+        else                                                            \
+            return F<R, D>(__VA_ARGS__);
+#define JAC_M2_SWITCH(depth, F, R, BAD, ...)                            \
+    switch (depth) {                                                    \
+        JAC_M2_CASE(F, R, 1, BAD, __VA_ARGS__)                          \
+        JAC_M2_CASE(F, R, 2, BAD, __VA_ARGS__)                          \
+        JAC_M2_CASE(F, R, 3, BAD, __VA_ARGS__)                          \
+        JAC_M2_CASE(F, R, 4, BAD, __VA_ARGS__)                          \
+        JAC_M2_CASE(F, R, 5, BAD, __VA_ARGS__)                          \
+        JAC_M2_CASE(F, R, 6, BAD, __VA_ARGS__)                          \
+        JAC_M2_CASE(F, R, 7, BAD, __VA_ARGS__)                          \
+        JAC_M2_CASE(F, R, 8, BAD, __VA_ARGS__)                          \
+    default:                                                            \
+        return BAD;                                                     \
     }
-}
 
 template <typename R>
-int64_t march2d_strips(const Geom &g, int depth) {
-    const int64_t nw = march2d_work_items<R>(g, depth, g.n[1]);  // one tile per strip
-    return nw;
+int march2d_waves_per_cu(int depth, int mode, int deep) {
+    JAC_M2_SWITCH(depth, m2_waves_per_cu_t, R, 0, mode, deep)
 }
 
 template <typename R>
 int64_t march2d_work_items(const Geom &g, int depth, int rows) {
-    switch (depth) {
-    case 1: return m2_nwork<R, 1>(g, rows, nullptr);
-    case 2: return m2_nwork<R, 2>(g, rows, nullptr);
-    case 3: return m2_nwork<R, 3>(g, rows, nullptr);
-    case 4: return m2_nwork<R, 4>(g, rows, nullptr);
-    case 5: return m2_nwork<R, 5>(g, rows, nullptr);
-    case 6: return m2_nwork<R, 6>(g, rows, nullptr);
-    case 7: return m2_nwork<R, 7>(g, rows, nullptr);
-    case 8: return m2_nwork<R, 8>(g, rows, nullptr);
-    default: return -1;
-    }
+    JAC_M2_SWITCH(depth, m2_nwork, R, (int64_t)-1, g, rows, nullptr)
 }
 
-template <>
-hipError_t launch_sweep2d_march<float>(const Geom &g, const void *uin, void *uout, const void *b,
-                                       double *res, double *gacc, int depth, int rows,
-                                       hipStream_t st, int64_t *nwork, int nt) {
-    switch (depth) {
-    case 1: return m2_launch_t<float, 1>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
-    case 2: return m2_launch_t<float, 2>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
-    case 3: return m2_launch_t<float, 3>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
-    case 4: return m2_launch_t<float, 4>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
-    case 5: return m2_launch_t<float, 5>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
-    case 6: return m2_launch_t<float, 6>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
-    case 7: return m2_launch_t<float, 7>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
-    case 8: return m2_launch_t<float, 8>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
-    default: return hipErrorInvalidValue;
-    }
+template <typename R>
+int64_t march2d_strips(const Geom &g, int depth) {
+    return march2d_work_items<R>(g, depth, g.n[1]);  // one tile per strip
 }
 
-template <>
-hipError_t launch_sweep2d_march<double>(const Geom &g, const void *uin, void *uout, const void *b,
-                                        double *res, double *gacc, int depth, int rows,
-                                        hipStream_t st, int64_t *nwork, int nt) {
-    switch (depth) {
-    case 1: return m2_launch_t<double, 1>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
-    case 2: return m2_launch_t<double, 2>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
-    case 3: return m2_launch_t<double, 3>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
-    case 4: return m2_launch_t<double, 4>(g, uin, uout, b, res, gacc, rows, st, nwork, nt);
-    default: return hipErrorInvalidValue;
-    }
+template <typename R>
+hipError_t launch_sweep2d_march(const Geom &g, const void *uin, void *uout, const void *b,
+                                double *res, double *gacc, int depth, int rows, hipStream_t st,
+                                int64_t *nwork, int nt, int deep) {
+    JAC_M2_SWITCH(depth, m2_launch_t, R, hipErrorInvalidValue, g, uin, uout, b, res, gacc, rows,
+                  st, nwork, nt, deep)
 }
 
 template <typename R>
 int64_t march2d_batch_work(const Geom &g, int depth, int rows, int *nseg) {
-    switch (depth) {
-    case 1: return m2_nwork<R, 1>(g, rows, nseg);
-    case 2: return m2_nwork<R, 2>(g, rows, nseg);
-    case 3: return m2_nwork<R, 3>(g, rows, nseg);
-    case 4: return m2_nwork<R, 4>(g, rows, nseg);
-    case 5: return m2_nwork<R, 5>(g, rows, nseg);
-    case 6: return m2_nwork<R, 6>(g, rows, nseg);
-    case 7: return m2_nwork<R, 7>(g, rows, nseg);
-    case 8: return m2_nwork<R, 8>(g, rows, nseg);
-    default: return -1;
-    }
-}
-
-template <typename R, int T>
-static hipError_t m2b_launch_t(const BatchGrid *grids, const int *prefix, int ngrids,
-                               const int *active, const int *pass_count, double *res, bool store,
-                               int rows, int nwork, hipStream_t st) {
-    const int grid = (nwork + 3) / 4;
-    hipLaunchKernelGGL((k_march2d_batch<R, T>), dim3(grid), dim3(256), 0, st, grids, prefix,
-                       ngrids, active, pass_count, res, store ? 1 : 0, rows, nwork);
-    return hipGetLastError();
+    JAC_M2_SWITCH(depth, m2_nwork, R, (int64_t)-1, g, rows, nseg)
 }
 
 template <typename R>
 hipError_t launch_march2d_batch(const BatchGrid *grids, const int *prefix, int ngrids,
                                 const int *active, const int *pass_count, double *res, bool store,
-                                int depth, int rows, int nwork, hipStream_t st) {
+                                int depth, int rows, int nwork, hipStream_t st, int deep) {
     if (nwork <= 0) return hipSuccess;
-    switch (depth) {
-    case 1: return m2b_launch_t<R, 1>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
-    case 2: return m2b_launch_t<R, 2>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
-    case 3: return m2b_launch_t<R, 3>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
-    case 4: return m2b_launch_t<R, 4>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
-    case 5: return m2b_launch_t<R, 5>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
-    case 6: return m2b_launch_t<R, 6>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
-    case 7: return m2b_launch_t<R, 7>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
-    case 8: return m2b_launch_t<R, 8>(grids, prefix, ngrids, active, pass_count, res, store, rows, nwork, st);
-    default: return hipErrorInvalidValue;
-    }
+    JAC_M2_SWITCH(depth, m2b_launch_t, R, hipErrorInvalidValue, grids, prefix, ngrids, active,
+                  pass_count, res, store, rows, nwork, st, deep)
 }
 
+template hipError_t launch_sweep2d_march<float>(const Geom &, const void *, void *, const void *,
+                                                double *, double *, int, int, hipStream_t,
+                                                int64_t *, int, int);
+template hipError_t launch_sweep2d_march<double>(const Geom &, const void *, void *, const void *,
+                                                 double *, double *, int, int, hipStream_t,
+                                                 int64_t *, int, int);
 template int64_t march2d_batch_work<float>(const Geom &, int, int, int *);
 template int64_t march2d_batch_work<double>(const Geom &, int, int, int *);
 template hipError_t launch_march2d_batch<float>(const BatchGrid *, const int *, int, const int *,
                                                 const int *, double *, bool, int, int, int,
-                                                hipStream_t);
+                                                hipStream_t, int);
 template hipError_t launch_march2d_batch<double>(const BatchGrid *, const int *, int, const int *,
                                                  const int *, double *, bool, int, int, int,
-                                                 hipStream_t);
+                                                 hipStream_t, int);
 template int64_t march2d_work_items<float>(const Geom &, int, int);
 template int64_t march2d_work_items<double>(const Geom &, int, int);
-template int march2d_waves_per_cu<float>(int, int);
-template int march2d_waves_per_cu<double>(int, int);
+template int march2d_waves_per_cu<float>(int, int, int);
+template int march2d_waves_per_cu<double>(int, int, int);
 template int64_t march2d_strips<float>(const Geom &, int);
 template int64_t march2d_strips<double>(const Geom &, int);
+
+#endif  // JAC_MARCH2D_DEPTH
 
 }  // namespace jac

@@ -38,14 +38,15 @@ hipError_t launch_sweep_local(const Geom &g, const void *uin, void *uout, const 
 template <typename R>
 hipError_t launch_sweep2d_march(const Geom &g, const void *uin, void *uout, const void *b,
                                 double *res, double *gacc, int depth, int rows, hipStream_t st,
-                                int64_t *nwork, int nt = 0);
+                                int64_t *nwork, int nt = 0, int deep = 0);
 // Work items (waves) of one march launch; -1 for an unknown depth.
 template <typename R>
 int64_t march2d_work_items(const Geom &g, int depth, int rows);
 // Resident waves per CU of the depth-`depth` march kernel in `mode`
-// (0 Laplace, 1 Poisson, 2 adjoint); 0 if unknown.
+// (0 Laplace, 1 Poisson, 2 adjoint; deep: the three-rows-ahead kernel); 0 if
+// unknown.
 template <typename R>
-int march2d_waves_per_cu(int depth, int mode);
+int march2d_waves_per_cu(int depth, int mode, int deep = 0);
 // Strips (work items per tile row) of the depth-`depth` march kernel.
 template <typename R>
 int64_t march2d_strips(const Geom &g, int depth);
@@ -59,7 +60,7 @@ int march2d_depths(int dtype, const int **list);
 template <typename R>
 hipError_t launch_march2d_batch(const BatchGrid *grids, const int *prefix, int ngrids,
                                 const int *active, const int *pass_count, double *res, bool store,
-                                int depth, int rows, int nwork, hipStream_t st);
+                                int depth, int rows, int nwork, hipStream_t st, int deep = 0);
 // Work items of one grid at this depth / tile height; tiles per strip in *nseg.
 template <typename R>
 int64_t march2d_batch_work(const Geom &g, int depth, int rows, int *nseg);

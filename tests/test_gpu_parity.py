@@ -72,16 +72,44 @@ def test_2d_bit_exact_all_depths(device, dtype, case):
     depths = list(range(1, jb.jacobi_max_depth(2, code) + 1))
     for depth in depths:
         for rows in (0, 8, 64):
-            say("2d case=%s dtype=%s depth=%d rows=%d" % (case, np.dtype(dtype).name, depth, rows))
-            got, _ = run_device(U0, f, h2, K, (bx, by), dtype, device, depth=depth, rows=rows)
-            assert_bits(got, want, "2d %s depth %d rows %d" % (case, depth, rows))
-    got, _ = run_device(U0, None, h2, K, (bx, by), dtype, device, depth=depths[-1])
-    assert_bits(got, want_l, "2d laplace %s" % (case,))
+            for fl in (0, jb.JACOBI_FLAG_DEEP_PREFETCH):
+                say("2d case=%s dtype=%s depth=%d rows=%d flags=%d"
+                    % (case, np.dtype(dtype).name, depth, rows, fl))
+                got, _ = run_device(U0, f, h2, K, (bx, by), dtype, device, depth=depth, rows=rows,
+                                    flags=fl)
+                assert_bits(got, want, "2d %s depth %d rows %d flags %d" % (case, depth, rows, fl))
+    for fl in (0, jb.JACOBI_FLAG_DEEP_PREFETCH):
+        got, _ = run_device(U0, None, h2, K, (bx, by), dtype, device, depth=depths[-1], flags=fl)
+        assert_bits(got, want_l, "2d laplace %s flags %d" % (case, fl))
     got, _ = run_device(U0, f, h2, K, (bx, by), dtype, device, flags=jb.JACOBI_FLAG_EXPLICIT_HALO)
     assert_bits(got, want, "2d explicit halo %s" % (case,))
     got, _ = run_device(U0, f, h2, K, (bx, by), dtype, device, depth=depths[-1],
                         flags=jb.JACOBI_FLAG_NT_STORES)
     assert_bits(got, want, "2d non-temporal stores %s" % (case,))
+
+
+@pytest.mark.parametrize("flags", [0, 4])
+@pytest.mark.parametrize("case", [(37, 29, 3, 4, 13), (513, 260, 3, 5, 25), (1, 1, 1, 1, 3)])
+def test_2d_residuals_and_states(device, case, flags):
+    """solve() with a residual every 4 sweeps (the residual folded into the
+    first pass of each interval): states bit-exact with the FP32 oracle twin,
+    residuals within 1e-12 of the FP64 residuals of the oracle's states, for
+    Poisson and Laplace, at the deepest depth and at depth 3."""
+    import paper_2303_02543_amd as jb
+    nx, ny, bx, by, K = case
+    U0 = RNG.uniform(0, 1, (ny + 2, nx + 2))
+    f = RNG.standard_normal((ny, nx)) * 100
+    h2 = synthetic.spacing2(max(nx, ny))
+    for src in (f, None):
+        want, b = oracle_run(U0, src, h2, K, np.float32)
+        ores, _ = oracle_residuals(np.asarray(U0, dtype=np.float32), b, K, 4)
+        for depth in (3, jb.jacobi_max_depth(2, jb.JACOBI_F32)):
+            say("2d residuals case=%s depth=%d flags=%d source=%s"
+                % (case, depth, flags, src is not None))
+            got, res = run_device(U0, src, h2, K, (bx, by), np.float32, device, depth=depth,
+                                  flags=flags, check_every=4)
+            assert_bits(got, want, "2d %s depth %d flags %d" % (case, depth, flags))
+            np.testing.assert_allclose(res, ores, rtol=1e-12, atol=0)
 
 
 # --------------------------------------------------------------- small 3D
