@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # FP32 vector ALU peak without packed or fused instructions:
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T ops/s
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-FLOPS_PER_UPDATE = 6  # (W+E), (S+N), sum, +b, *w  -> 4 adds + 1 add + 1 mul
+FLOPS_PER_UPDATE = 5  # (W+E), (S+N), their sum, +b: 4 adds; *w: 1 mul
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep2d_march_poisson8192.json")
 SWEEP_SOURCE = os.path.join(ROOT, "paper_2303_02543_amd", "csrc", "k_march2d.hip")
 
@@ -350,7 +350,10 @@ def main():
     if flags & jb.JACOBI_FLAG_EXPLICIT_HALO:
         kname = "k_sweep_local<float, true>"
     else:
-        kname = "k_march2d<float, %d, 1>" % d_dom
+        # Poisson pass kernel of depth d_dom and its prefetch distance; the
+        # traffic record aggregates its two residual variants
+        kname = "k_march2d<float, %d, %d, 1>" % (
+            d_dom, 3 if flags & jb.JACOBI_FLAG_DEEP_PREFETCH else 1)
     traffic = traffic_for(kname, bytes_per_launch)
     hbm_frac = hbm_gbs / HBM_PEAK_GBS
     alu_frac = alu_tops / ALU_PEAK_TOPS
@@ -393,7 +396,8 @@ def main():
             "grid": [N, N], "blocks": list(BLOCKS), "sweeps": SWEEPS,
             "check_every": CHECK_EVERY, "t_depth": depth, "rows": rows,
             "explicit_halo": bool(flags & jb.JACOBI_FLAG_EXPLICIT_HALO),
-            "nt_stores": bool(flags & jb.JACOBI_FLAG_NT_STORES), "flags": flags,
+            "nt_stores": bool(flags & jb.JACOBI_FLAG_NT_STORES),
+            "deep_prefetch": bool(flags & jb.JACOBI_FLAG_DEEP_PREFETCH), "flags": flags,
             "parallelism": "single GPU",
         },
         "roofline": roof,

@@ -209,7 +209,7 @@ int balanced_rows(const jacobi_s *h, int depth, int mode, int rounds, int deep) 
 // explicit halos (depth 1) for 3D.
 int default_depth(const jacobi_s *h) {
     if (h->g.ndim == 3) return 1;
-    return h->dtype == JACOBI_F32 ? 8 : 4;
+    return h->dtype == JACOBI_F32 ? 12 : 4;
 }
 
 // The 2D pass kernels address a lane's chunk as a 32-bit byte offset from a
@@ -873,7 +873,7 @@ const char *jacobi_last_error(void) { return g_last_error.c_str(); }
 // ====================================================================== batch
 namespace {
 
-constexpr int kMaxDepth = 8;
+constexpr int kMaxDepth = 16;  // deepest pass kernel (FP32)
 
 struct BatchLayout {
     std::vector<Geom> geoms;

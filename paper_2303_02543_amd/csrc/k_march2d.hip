@@ -372,8 +372,8 @@ __device__ __forceinline__ void m2_body(const Geom &g, const R *__restrict__ uin
     }
 }
 
-// One work item (wave): strip/tile number `wid` of a grid with `nseg` tiles
-// per strip.  wid is wave-uniform.  RES: accumulate the residual partial into
+// One work item (wave): tile number `wid` of a grid with `nseg` tiles per
+// strip.  wid is wave-uniform.  RES: accumulate the residual partial into
 // *res_slot.  bs_wave: the wave's LDS source ring.
 template <typename R, int T, int P, int MODE, bool RES>
 __device__ __forceinline__ void m2_run(const Geom &g, const R *__restrict__ uin,
@@ -385,7 +385,10 @@ __device__ __forceinline__ void m2_run(const Geom &g, const R *__restrict__ uin,
     constexpr bool SRC = MODE == MODE_POISSON;
     constexpr int V = S::V;
     const int lane = threadIdx.x & 63;
-    const int strip = wid / nseg, seg = wid % nseg;
+    // adjacent work items are adjacent strips of one row segment, so the
+    // waves of a workgroup walk neighbouring columns of the same rows
+    const int nstrips = (g.n[0] + S::OW - 1) / S::OW;
+    const int strip = wid % nstrips, seg = wid / nstrips;
     const int nx = g.n[0], ny = g.n[1];
     const int a = strip * S::OW - S::A0;  // first column held by the strip
     MLane L;
@@ -423,6 +426,7 @@ __device__ __forceinline__ void m2_run(const Geom &g, const R *__restrict__ uin,
     // rows r0 .. r1 + P are read; an interior tile reads only grid rows and
     // columns, none of them on the ring
     static_assert(MODE != MODE_ADJOINT || P == 1, "the adjoint pass prefetches one row");
+    static_assert(MODE != MODE_ADJOINT || T + 1 <= S::RA, "adjoint accumulator ring too small");
     const int r0 = L.oy0 - T;
     const bool edge = a < 0 || a + S::W > nx || r0 < 0 || L.r1 + P > ny - 1;
     if (edge)
@@ -520,11 +524,18 @@ static hipError_t m2_launch_p(const Geom &g, const void *uin, void *uout, const 
                               hipStream_t st, int nt) {
     const int grid = (nwork + 3) / 4;
     const R *bb = (const R *)b;
-    if (gacc)
-        hipLaunchKernelGGL((k_march2d<R, T, 1, MODE_ADJOINT, false>), dim3(grid), dim3(256), 0, st,
-                           g, (const R *)uin, (R *)uout, (const R *)nullptr, (double *)nullptr,
-                           gacc, nseg, rows, nwork, nt);
-    else if (b && res)
+    if (gacc) {
+        // adjoint passes go to depth 8 (the accumulator ring holds T + 1 rows)
+        if constexpr (T > 8) {
+            return hipErrorInvalidValue;
+        } else {
+            hipLaunchKernelGGL((k_march2d<R, T, 1, MODE_ADJOINT, false>), dim3(grid), dim3(256), 0,
+                               st, g, (const R *)uin, (R *)uout, (const R *)nullptr,
+                               (double *)nullptr, gacc, nseg, rows, nwork, nt);
+            return hipGetLastError();
+        }
+    }
+    if (b && res)
         hipLaunchKernelGGL((k_march2d<R, T, P, MODE_POISSON, true>), dim3(grid), dim3(256), 0, st,
                            g, (const R *)uin, (R *)uout, bb, res, (double *)nullptr, nseg, rows,
                            nwork, nt);
@@ -585,9 +596,12 @@ template <typename R, int T>
 int m2_waves_per_cu_t(int mode, int deep) {
     int blocks = 0;
     hipError_t e;
-    if (mode == MODE_ADJOINT)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 1, MODE_ADJOINT, false>, 256, 0);
-    else if (mode == MODE_POISSON && deep)
+    if (mode == MODE_ADJOINT) {
+        if constexpr (T > 8)
+            return 0;
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 1, MODE_ADJOINT, false>, 256, 0);
+    } else if (mode == MODE_POISSON && deep)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 3, MODE_POISSON, false>, 256, 0);
     else if (mode == MODE_POISSON)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 1, MODE_POISSON, false>, 256, 0);
@@ -614,7 +628,7 @@ JAC_M2_INSTANTIATE(double, JAC_MARCH2D_DEPTH)
 
 #else  // dispatch object
 
-static const int kDepthsF32[] = {1, 2, 3, 4, 5, 6, 7, 8};
+static const int kDepthsF32[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 16};
 static const int kDepthsF64[] = {1, 2, 3, 4};
 
 int march2d_depths(int dtype, const int **list) {
@@ -644,6 +658,9 @@ int march2d_depths(int dtype, const int **list) {
         JAC_M2_CASE(F, R, 6, BAD, __VA_ARGS__)                          \
         JAC_M2_CASE(F, R, 7, BAD, __VA_ARGS__)                          \
         JAC_M2_CASE(F, R, 8, BAD, __VA_ARGS__)                          \
+        JAC_M2_CASE(F, R, 10, BAD, __VA_ARGS__)                         \
+        JAC_M2_CASE(F, R, 12, BAD, __VA_ARGS__)                         \
+        JAC_M2_CASE(F, R, 16, BAD, __VA_ARGS__)                         \
     default:                                                            \
         return BAD;                                                     \
     }
