@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--cpu-full-seconds", type=float, default=45.0,
+                    help="run the whole workload on the oracle (and report the GPU result's "
+                         "error against it) when it is estimated to take at most this long")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched and adjoint measurements")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -193,6 +196,7 @@ def bench_poisson3d(plain_glups):
         Ud = torch.from_numpy(U0.astype(np_dt)).to(dev)
         s = jb.Solver((n, n, n), (8, 8, 8), t_dt, device=dev)
         try:
+            s.autotune(R, with_source=True)
             res = torch.empty(jb.residual_count(K, R), dtype=torch.float64, device=dev)
 
             def step():
@@ -208,15 +212,64 @@ def bench_poisson3d(plain_glups):
             dt = time.perf_counter() - t0
             p = s.profile_read(0)
             s.profile(False)
+            tuning = s.get_tuning()
         finally:
             s.close()
         es = 4 if name == "f32" else 8
         kms = p["ms"] / max(p["launches"], 1)
+        d3, z3, f3 = tuning
         out[name] = {"glups": round(float(n) ** 3 * K / dt / 1e9, 3),
+                     "zseg": z3, "flags": f3,
                      "pass_kernel_avg_ms": round(kms, 5),
                      "pass_kernel_hbm_gbs_alg": round(3 * es * float(n) ** 3 / (kms * 1e-3) / 1e9, 1),
                      "ratio_vs_plain_2d": round(float(n) ** 3 * K / dt / 1e9 / plain_glups, 4)}
         del fd, Ud
+    return out
+
+
+def bench_plain2d():
+    """Plain sweeps (one sweep per kernel) of the 8192^2 Poisson grid in 16x16
+    blocks: the block-local sweep after an explicit halo exchange (the step
+    order of the paper's proxy) and the fused pass at depth 1 (halo cells read
+    from their owning blocks), FP32 and FP64.  HBM figures are algorithmic
+    bytes (state read + source read + state write per cell) over the sweep
+    kernel's own time (HIP events on the solver's stream)."""
+    import numpy as np
+    import torch
+    import paper_2303_02543_amd as jb
+    import synthetic
+    dev = torch.device("cuda:0")
+    n, K = N, 50
+    f64 = synthetic.gaussian_sum(n, 2, 2)
+    h2 = synthetic.spacing2(n)
+    out = {"workload": "2D 5-point Poisson %dx%d, 16x16 blocks, %d plain sweeps" % (n, n, K)}
+    for name, np_dt, t_dt in (("f32", np.float32, torch.float32), ("f64", np.float64, torch.float64)):
+        es = 4 if name == "f32" else 8
+        s = jb.Solver((n, n), BLOCKS, t_dt, device=dev)
+        try:
+            s.set_source(torch.from_numpy(f64.astype(np_dt)).to(dev), h2)
+            s.set_state(torch.zeros((n + 2, n + 2), dtype=t_dt, device=dev))
+            rec = {}
+            for form, flags in (("explicit_halo", jb.JACOBI_FLAG_EXPLICIT_HALO), ("fused", 0)):
+                s.set_tuning(1, 0, flags)
+                s.sweep(K)
+                torch.cuda.synchronize()
+                s.profile(True)
+                t0 = time.perf_counter()
+                s.sweep(K)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                p = s.profile_read(0)
+                s.profile(False)
+                kms = p["ms"] / max(p["launches"], 1)
+                gbs = 3 * es * float(n) ** 2 / (kms * 1e-3) / 1e9
+                rec[form] = {"glups": round(float(n) ** 2 * K / dt / 1e9, 3),
+                             "sweep_kernel_avg_ms": round(kms, 5),
+                             "sweep_kernel_hbm_gbs_alg": round(gbs, 1),
+                             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+            out[name] = rec
+        finally:
+            s.close()
     return out
 
 
@@ -243,31 +296,51 @@ def traffic_for(kernel_name, launches_alg_bytes):
     return k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(U0_np, f_np, h2, target_seconds):
-    """Time the FP64 oracle on the full grid for a bounded number of sweeps plus
-    one residual (a sample of the workload), return the JSON object."""
+def cpu_baseline(U0_np, f_np, h2, target_seconds, full_max_seconds, gpu_final):
+    """Time the FP64 oracle on the host's cores.  When the whole workload
+    (SWEEPS sweeps, a residual every CHECK_EVERY) is estimated to fit in
+    full_max_seconds it is run in full and the GPU's final FP32 state is
+    compared with it (max-abs error and max-abs error / max-abs value over the
+    interior); otherwise a bounded sample of sweeps on the full grid is timed."""
     import numpy as np
     import oracle
     U = U0_np.astype(np.float64)
     b = oracle.scale_source(f_np.astype(np.float64), h2, np.float64)
     t0 = time.perf_counter()
-    U = oracle.sweep(U, b, 2)
-    dt2 = time.perf_counter() - t0
-    k = int(max(2, min(200, target_seconds / max(dt2 / 2, 1e-6))))
+    oracle.sweep(U, b, 2)
+    per_sweep = (time.perf_counter() - t0) / 2
+    cells = float(N) * N
+    out = {"unit": "GLUP/s", "cores": oracle.num_threads(), "kind": "oracle"}
+    if per_sweep * SWEEPS <= full_max_seconds:
+        t0 = time.perf_counter()
+        res = [oracle.residual(U, b)]
+        k = 0
+        while k < SWEEPS:
+            step = min(CHECK_EVERY, SWEEPS - k)
+            U = oracle.sweep(U, b, step)
+            k += step
+            res.append(oracle.residual(U, b))
+        dt = time.perf_counter() - t0
+        out["value"] = round(cells * SWEEPS / dt / 1e9, 4)
+        out["sample"] = ("the whole workload: FP64 oracle, %dx%d, %d sweeps + %d residuals "
+                         "(%.1f s)" % (N, N, SWEEPS, len(res), dt))
+        gi = np.asarray(gpu_final, dtype=np.float64)[1:-1, 1:-1]
+        oi = U[1:-1, 1:-1]
+        err = float(np.max(np.abs(gi - oi)))
+        out["error_vs_fp64_oracle"] = {
+            "max_abs": err, "rel": err / float(np.max(np.abs(oi))), "bound": 1e-5,
+            "oracle_final_residual": res[-1]}
+        return out
+    k = int(max(2, min(200, target_seconds / max(per_sweep, 1e-6))))
     t0 = time.perf_counter()
     U = oracle.sweep(U, b, k)
     r = oracle.residual(U, b)
     dt = time.perf_counter() - t0
-    cells = float(N) * N
-    return {
-        "value": round(cells * k / dt / 1e9, 4),
-        "unit": "GLUP/s",
-        "cores": oracle.num_threads(),
-        "kind": "oracle",
-        "sample": "FP64 oracle on the full %dx%d grid: %d sweeps + 1 residual (%.1f s)"
-                  % (N, N, k, dt),
-        "residual_check": r if math.isfinite(r) else None,
-    }
+    out["value"] = round(cells * k / dt / 1e9, 4)
+    out["sample"] = ("FP64 oracle on the full %dx%d grid: %d sweeps + 1 residual (%.1f s)"
+                     % (N, N, k, dt))
+    out["residual_check"] = r if math.isfinite(r) else None
+    return out
 
 
 def main():
@@ -409,8 +482,10 @@ def main():
         out["batched"] = bench_batched(glups)
         out["adjoint"] = bench_adjoint(glups)
         out["poisson3d"] = bench_poisson3d(glups)
+        out["plain2d"] = bench_plain2d()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(U0_np, f32, h2, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(U0_np, f32, h2, args.cpu_seconds,
+                                           args.cpu_full_seconds, U_out.cpu().numpy())
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -149,9 +149,13 @@ int jacobi_residual(jacobi_t h, double *res_host);
 int jacobi_solve(jacobi_t h, int64_t n_iter, int64_t check_every, double *res_dev);
 
 /* Choose the sweep schedule.  t_depth: sweeps per pass (temporal blocking,
- * 1..jacobi_max_depth(); 0 = library default), rows: rows per tile
- * (0 = default), flags: jacobi_flags.  Bit-neutral: every choice gives the
- * same results. */
+ * 1..jacobi_max_depth(); 0 = library default; a depth without a compiled
+ * kernel is run as passes of the nearest smaller compiled depths).
+ * rows (0 = default): rows per tile of the 2D pass (>= 8), z planes per
+ * work item of the 3D pass (>= 8), or, with JACOBI_FLAG_EXPLICIT_HALO on a
+ * 2D grid, rows per work item of the block-local sweep (>= 1).
+ * flags: jacobi_flags.  JACOBI_E_INVAL for values out of range.
+ * Bit-neutral: every choice gives the same results. */
 int jacobi_set_tuning(jacobi_t h, int t_depth, int rows, int flags);
 int jacobi_get_tuning(jacobi_t h, int *t_depth, int *rows, int *flags);
 

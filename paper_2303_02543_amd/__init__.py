@@ -463,9 +463,12 @@ class Solver:
         return jacobi_get_layout(self.h)
 
     def close(self):
-        if getattr(self, "h", None) is not None:
-            jacobi_destroy(self.h)
+        # the library frees the handle even when it reports an error, so
+        # forget it first: a second destroy would free it twice
+        h = getattr(self, "h", None)
+        if h is not None:
             self.h = None
+            jacobi_destroy(h)
 
     def __del__(self):
         try:
@@ -548,9 +551,10 @@ class Batch:
         return out
 
     def close(self):
-        if getattr(self, "h", None) is not None:
-            jacobi_batch_destroy(self.h)
+        h = getattr(self, "h", None)
+        if h is not None:
             self.h = None
+            jacobi_batch_destroy(h)
 
     def __del__(self):
         try:

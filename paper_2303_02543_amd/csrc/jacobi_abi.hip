@@ -345,7 +345,8 @@ int do_sweep(jacobi_t h, int64_t n, double *res_first) {
         for (int64_t k = 0; k < n; ++k) {
             int rc = prof_begin(h);
             if (rc) return rc;
-            HIP_TRY(jac::launch_sweep_local<R>(h->g, h->u[h->cur], h->u[h->cur ^ 1], b, h->stream),
+            HIP_TRY(jac::launch_sweep_local<R>(h->g, h->u[h->cur], h->u[h->cur ^ 1], b, h->stream,
+                                               h->rows),
                     "sweep launch");
             rc = prof_end(h, 1);
             if (rc) return rc;
@@ -662,8 +663,13 @@ int jacobi_set_tuning(jacobi_t h, int t_depth, int rows, int flags) {
     const int md = max_depth(h->g.ndim, h->dtype);
     if (t_depth < 0 || t_depth > md)
         return fail(JACOBI_E_INVAL, "t_depth must be in [0, %d] (got %d)", md, t_depth);
-    if (rows < 0 || (rows > 0 && rows < kMinRows) || rows > (1 << 20))
-        return fail(JACOBI_E_INVAL, "rows must be 0 or in [%d, 2^20] (got %d)", kMinRows, rows);
+    // rows: tile height of the 2D pass kernels and z segment of the 3D ones
+    // (>= kMinRows, which sizes the residual partials); rows per work item of
+    // the explicit 2D sweep (>= 1)
+    const int min_rows =
+        ((flags & JACOBI_FLAG_EXPLICIT_HALO) && h->g.ndim == 2) ? 1 : kMinRows;
+    if (rows < 0 || (rows > 0 && rows < min_rows) || rows > (1 << 20))
+        return fail(JACOBI_E_INVAL, "rows must be 0 or in [%d, 2^20] (got %d)", min_rows, rows);
     if (flags & ~(JACOBI_FLAG_EXPLICIT_HALO | JACOBI_FLAG_NT_STORES | JACOBI_FLAG_DEEP_PREFETCH))
         return fail(JACOBI_E_INVAL, "unknown flags 0x%x", flags);
     h->depth = t_depth;
@@ -779,6 +785,8 @@ int jacobi_autotune(jacobi_t h, int64_t n_sweeps, int with_source, int *t_depth,
         };
         std::vector<Cand> cands;
         cands.push_back({1, 0, JACOBI_FLAG_EXPLICIT_HALO});
+        if (h->g.ndim == 2)
+            for (int rg : {1, 2, 4, 8}) cands.push_back({1, rg, JACOBI_FLAG_EXPLICIT_HALO});
         if (h->g.ndim == 3) {
             static const int kZseg[] = {8, 16, 32, 64, 128};
             for (int z : kZseg)

@@ -22,9 +22,10 @@ template <typename R>
 hipError_t launch_halo_exchange(const Geom &g, void *s, hipStream_t st);
 
 // One sweep of every block from its own storage (halos must be current).
+// 2D: rg rows per work item (0: a default).
 template <typename R>
 hipError_t launch_sweep_local(const Geom &g, const void *uin, void *uout, const void *b,
-                              hipStream_t st);
+                              hipStream_t st, int rg = 0);
 
 // `depth` sweeps in one pass over the whole 2D grid, reading face neighbours'
 // cells from their owning blocks.  uout may be NULL (no output: residual
