@@ -58,6 +58,33 @@ __device__ __forceinline__ double shift_down(double old, double src) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Shifts within each 16-lane row of the wave through DPP (row_shr:1 /
+// row_shl:1).  All 64 lanes must be active.
+// row_shift_up: lane i receives src of lane i-1 of its row; the row's first
+// lane keeps `old`.
+__device__ __forceinline__ float row_shift_up(float old, float src) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src),
+                                                      0x111, 0xf, 0xf, false));
+}
+// row_shift_down: lane i receives src of lane i+1 of its row; the row's last
+// lane keeps `old`.
+__device__ __forceinline__ float row_shift_down(float old, float src) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src),
+                                                      0x101, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double row_shift_up(double old, double src) {
+    const long long o = __double_as_longlong(old), s = __double_as_longlong(src);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)s, 0x111, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), 0x111, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double row_shift_down(double old, double src) {
+    const long long o = __double_as_longlong(old), s = __double_as_longlong(src);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)s, 0x101, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), 0x101, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Deterministic wave-wide FP64 sum (fixed xor-butterfly order).
 __device__ __forceinline__ double wave_sum(double a) {
 #pragma unroll

@@ -133,9 +133,10 @@ int plan(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, Geom *
     // workgroup of the standalone residual kernel
     size_t cap = ((size_t)g->n[0] / 32 + 2) * ((size_t)g->n[1] * g->n[2] / kMinRows + 2);
     if (ndim == 3) {
-        // 3D pass: one work item per (strip of >= 128 columns, row, z segment)
-        const size_t c3 = ((size_t)g->n[0] / 128 + 1) * (size_t)g->n[1] *
-                          ((size_t)g->n[2] / kMinRows + 1);
+        // 3D pass: 4 partials (one per wave) per work item of (strip of
+        // >= 32 columns, 16 rows, z segment of >= kMinRows planes)
+        const size_t c3 = ((size_t)g->n[0] / 32 + 2) * 4 * ((size_t)g->n[1] / 16 + 2) *
+                          ((size_t)g->n[2] / kMinRows + 2);
         if (c3 > cap) cap = c3;
     }
     if (cap < (size_t)jac::kResidualGroups) cap = jac::kResidualGroups;
