@@ -1001,11 +1001,9 @@ int batch_tables(jacobi_batch_t b) {
         int *pre = &b->h_prefix[(size_t)d * (n + 1)];
         int64_t acc = 0;
         for (int i = 0; i < n; ++i) {
-            int nseg = 0;
             pre[i] = (int)acc;
-            const int64_t w = jac::march2d_batch_work<R>(b->bl.geoms[i], d, rows, &nseg);
+            const int64_t w = jac::march2d_batch_work<R>(b->bl.geoms[i], d, rows);
             if (w < 0) { acc = -1; break; }
-            b->h_grids[i].nseg = nseg;
             acc += w;
             if (acc > 0x3fffffff) return fail(JACOBI_E_INVAL, "batch work exceeds 2^30 items");
         }

@@ -46,8 +46,6 @@ struct BatchGrid {
     Geom g;
     void *u[2];     // the two state buffers
     const void *b;  // blocked source
-    int nseg;       // tiles per strip at the batch's tile height
-    int pad;
 };
 
 // Device-side state of a batched solve (arrays of one entry per grid).

@@ -17,8 +17,9 @@
 // strip arrive by one scalar load per row.  Level T is the pass's output.
 // A strip recomputes T - 1 columns on each side and a segment T rows on each
 // side; only the strip's output lanes [L0, L1) and the segment's own rows
-// are stored.  Rows are loaded one step ahead of use, straight into their
-// ring slot, so no register copies are needed.  A source row waits in
+// are stored.  Rows are loaded P steps ahead of use (P = 1, or 3 with the
+// deep-prefetch option), straight into their ring slot, so no register
+// copies are needed.  A source row waits in
 // registers for one step before it is written to the wave's LDS ring (it is
 // first read one step after that), so the wait for its load overlaps a whole
 // step of arithmetic instead of stalling the step that issued it.
@@ -116,8 +117,8 @@ struct MRegs {
 struct MLane {
     uint32_t lane_b, edge_b, src_b;  // byte offsets of the lane's chunk / edge / source
     bool ld, ldb, lde;
-    bool upd[8];                     // per-element: interior column (ring strips)
-    bool st[8];                      // per-element: interior output column (ring strips)
+    bool upd[8];                     // per-element: interior column (edge tiles)
+    bool st[8];                      // per-element: interior output column (edge tiles)
     bool out_lane;                   // lane holds output columns
     bool nt;                         // non-temporal output stores
     int c;                           // global column of the lane's first element
@@ -372,14 +373,14 @@ __device__ __forceinline__ void m2_body(const Geom &g, const R *__restrict__ uin
     }
 }
 
-// One work item (wave): tile number `wid` of a grid with `nseg` tiles per
-// strip.  wid is wave-uniform.  RES: accumulate the residual partial into
+// One work item (wave): tile number `wid` of a grid cut into tiles of
+// `rows` rows.  wid is wave-uniform.  RES: accumulate the residual partial into
 // *res_slot.  bs_wave: the wave's LDS source ring.
 template <typename R, int T, int P, int MODE, bool RES>
 __device__ __forceinline__ void m2_run(const Geom &g, const R *__restrict__ uin,
                                        R *__restrict__ uout, const R *__restrict__ bsrc,
                                        double *__restrict__ res_slot, double *__restrict__ gacc,
-                                       int wid, int nseg, int rows, Chunk<R, M2<R, T, P>::V> *bs_wave,
+                                       int wid, int rows, Chunk<R, M2<R, T, P>::V> *bs_wave,
                                        bool nt) {
     using S = M2<R, T, P>;
     constexpr bool SRC = MODE == MODE_POISSON;
@@ -443,8 +444,8 @@ __global__ __launch_bounds__(256) void k_march2d(Geom g, const R *__restrict__ u
                                                  R *__restrict__ uout,
                                                  const R *__restrict__ bsrc,
                                                  double *__restrict__ res,
-                                                 double *__restrict__ gacc, int nseg, int rows,
-                                                 int nwork, int nt) {
+                                                 double *__restrict__ gacc, int rows, int nwork,
+                                                 int nt) {
     using S = M2<R, T, P>;
     constexpr bool SRC = MODE == MODE_POISSON;
     // per wave: a ring of RB source rows, one 16-byte chunk per lane each
@@ -452,8 +453,8 @@ __global__ __launch_bounds__(256) void k_march2d(Geom g, const R *__restrict__ u
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int wid = __builtin_amdgcn_readfirstlane(lb * (blockDim.x >> 6) + (threadIdx.x >> 6));
     if (wid >= nwork) return;
-    m2_run<R, T, P, MODE, RES>(g, uin, uout, bsrc, RES ? res + wid : nullptr, gacc, wid, nseg,
-                               rows, &bsm[SRC ? (threadIdx.x >> 6) * S::RB * 64 : 0], nt != 0);
+    m2_run<R, T, P, MODE, RES>(g, uin, uout, bsrc, RES ? res + wid : nullptr, gacc, wid, rows,
+                               &bsm[SRC ? (threadIdx.x >> 6) * S::RB * 64 : 0], nt != 0);
 }
 
 // Batched pass: the work items of all grids of a batch in one launch.  Work
@@ -484,8 +485,8 @@ __global__ __launch_bounds__(256) void k_march2d_batch(const BatchGrid *__restri
     const R *uin = (const R *)grids[gi].u[par];
     R *uout = store ? (R *)grids[gi].u[par ^ 1] : nullptr;
     m2_run<R, T, P, MODE_POISSON, RES>(g, uin, uout, (const R *)grids[gi].b,
-                                    RES ? res + wid : nullptr, nullptr, wid - prefix[gi],
-                                    grids[gi].nseg, rows, &bsm[(threadIdx.x >> 6) * S::RB * 64],
+                                    RES ? res + wid : nullptr, nullptr, wid - prefix[gi], rows,
+                                    &bsm[(threadIdx.x >> 6) * S::RB * 64],
                                     false);
 }
 
@@ -520,8 +521,8 @@ int m2_waves_per_cu_t(int mode, int deep);
 
 template <typename R, int T, int P>
 static hipError_t m2_launch_p(const Geom &g, const void *uin, void *uout, const void *b,
-                              double *res, double *gacc, int rows, int nseg, int nwork,
-                              hipStream_t st, int nt) {
+                              double *res, double *gacc, int rows, int nwork, hipStream_t st,
+                              int nt) {
     const int grid = (nwork + 3) / 4;
     const R *bb = (const R *)b;
     if (gacc) {
@@ -531,26 +532,26 @@ static hipError_t m2_launch_p(const Geom &g, const void *uin, void *uout, const 
         } else {
             hipLaunchKernelGGL((k_march2d<R, T, 1, MODE_ADJOINT, false>), dim3(grid), dim3(256), 0,
                                st, g, (const R *)uin, (R *)uout, (const R *)nullptr,
-                               (double *)nullptr, gacc, nseg, rows, nwork, nt);
+                               (double *)nullptr, gacc, rows, nwork, nt);
             return hipGetLastError();
         }
     }
     if (b && res)
         hipLaunchKernelGGL((k_march2d<R, T, P, MODE_POISSON, true>), dim3(grid), dim3(256), 0, st,
-                           g, (const R *)uin, (R *)uout, bb, res, (double *)nullptr, nseg, rows,
-                           nwork, nt);
+                           g, (const R *)uin, (R *)uout, bb, res, (double *)nullptr, rows, nwork,
+                           nt);
     else if (b)
         hipLaunchKernelGGL((k_march2d<R, T, P, MODE_POISSON, false>), dim3(grid), dim3(256), 0, st,
                            g, (const R *)uin, (R *)uout, bb, (double *)nullptr, (double *)nullptr,
-                           nseg, rows, nwork, nt);
+                           rows, nwork, nt);
     else if (res)
         hipLaunchKernelGGL((k_march2d<R, T, P, MODE_LAPLACE, true>), dim3(grid), dim3(256), 0, st,
                            g, (const R *)uin, (R *)uout, (const R *)nullptr, res,
-                           (double *)nullptr, nseg, rows, nwork, nt);
+                           (double *)nullptr, rows, nwork, nt);
     else
         hipLaunchKernelGGL((k_march2d<R, T, P, MODE_LAPLACE, false>), dim3(grid), dim3(256), 0, st,
                            g, (const R *)uin, (R *)uout, (const R *)nullptr, (double *)nullptr,
-                           (double *)nullptr, nseg, rows, nwork, nt);
+                           (double *)nullptr, rows, nwork, nt);
     return hipGetLastError();
 }
 
@@ -558,13 +559,12 @@ template <typename R, int T>
 hipError_t m2_launch_t(const Geom &g, const void *uin, void *uout, const void *b, double *res,
                        double *gacc, int rows, hipStream_t st, int64_t *nwork_out, int nt,
                        int deep) {
-    int nseg = 0;
-    const int64_t nwork = m2_nwork<R, T>(g, rows, &nseg);
+    const int64_t nwork = m2_nwork<R, T>(g, rows, nullptr);
     if (nwork_out) *nwork_out = nwork;
-    if (nwork > 0x7fffffff) return hipErrorInvalidValue;
+    if (nwork > 0x7fffffff - 3) return hipErrorInvalidValue;
     if (deep && !gacc)
-        return m2_launch_p<R, T, 3>(g, uin, uout, b, res, gacc, rows, nseg, (int)nwork, st, nt);
-    return m2_launch_p<R, T, 1>(g, uin, uout, b, res, gacc, rows, nseg, (int)nwork, st, nt);
+        return m2_launch_p<R, T, 3>(g, uin, uout, b, res, gacc, rows, (int)nwork, st, nt);
+    return m2_launch_p<R, T, 1>(g, uin, uout, b, res, gacc, rows, (int)nwork, st, nt);
 }
 
 template <typename R, int T, int P>
@@ -640,8 +640,8 @@ int march2d_depths(int dtype, const int **list) {
     return (int)(sizeof(kDepthsF64) / sizeof(int));
 }
 
-// Calls F<R, depth>(args...) for a compiled depth (1..8 in FP32, 1..4 in
-// FP64); `bad` otherwise.
+// Calls F<R, depth>(args...) for a compiled depth (1..8, 10, 12, 16 in FP32,
+// 1..4 in FP64); `bad` otherwise.
 #define JAC_M2_CASE(F, R, D, BAD, ...)                                  \
     case D:                                                             \
         if constexpr (sizeof(R) == 8 && D > 4)                          \
@@ -689,8 +689,8 @@ hipError_t launch_sweep2d_march(const Geom &g, const void *uin, void *uout, cons
 }
 
 template <typename R>
-int64_t march2d_batch_work(const Geom &g, int depth, int rows, int *nseg) {
-    JAC_M2_SWITCH(depth, m2_nwork, R, (int64_t)-1, g, rows, nseg)
+int64_t march2d_batch_work(const Geom &g, int depth, int rows) {
+    JAC_M2_SWITCH(depth, m2_nwork, R, (int64_t)-1, g, rows, nullptr)
 }
 
 template <typename R>
@@ -708,8 +708,8 @@ template hipError_t launch_sweep2d_march<float>(const Geom &, const void *, void
 template hipError_t launch_sweep2d_march<double>(const Geom &, const void *, void *, const void *,
                                                  double *, double *, int, int, hipStream_t,
                                                  int64_t *, int, int);
-template int64_t march2d_batch_work<float>(const Geom &, int, int, int *);
-template int64_t march2d_batch_work<double>(const Geom &, int, int, int *);
+template int64_t march2d_batch_work<float>(const Geom &, int, int);
+template int64_t march2d_batch_work<double>(const Geom &, int, int);
 template hipError_t launch_march2d_batch<float>(const BatchGrid *, const int *, int, const int *,
                                                 const int *, double *, bool, int, int, int,
                                                 hipStream_t, int);

@@ -62,9 +62,9 @@ template <typename R>
 hipError_t launch_march2d_batch(const BatchGrid *grids, const int *prefix, int ngrids,
                                 const int *active, const int *pass_count, double *res, bool store,
                                 int depth, int rows, int nwork, hipStream_t st, int deep = 0);
-// Work items of one grid at this depth / tile height; tiles per strip in *nseg.
+// Work items of one grid at this depth / tile height.
 template <typename R>
-int64_t march2d_batch_work(const Geom &g, int depth, int rows, int *nseg);
+int64_t march2d_batch_work(const Geom &g, int depth, int rows);
 
 // One 3D sweep in one pass over the whole grid (k_march3d.hip), reading face
 // neighbours' cells from their owning blocks; zseg planes per work item.
