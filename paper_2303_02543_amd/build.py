@@ -22,7 +22,7 @@ SOURCES = ["jacobi_abi.hip", "k_layout.hip", "k_sweep.hip", "k_march2d.hip", "k_
            "k_residual.hip", "k_batch.hip"]
 # k_march2d.hip is compiled once per temporal depth (its kernels) and once
 # more for the depth dispatch; each entry: (source, object name, defines)
-MARCH2D_DEPTHS = list(range(1, 9)) + [10, 12, 16]
+MARCH2D_DEPTHS = list(range(1, 9)) + [10, 11, 12, 13, 14, 16]
 UNITS = ([(s, os.path.splitext(s)[0], []) for s in SOURCES] +
          [("k_march2d.hip", "k_march2d_d%d" % d, ["-DJAC_MARCH2D_DEPTH=%d" % d])
           for d in MARCH2D_DEPTHS])

@@ -628,7 +628,7 @@ JAC_M2_INSTANTIATE(double, JAC_MARCH2D_DEPTH)
 
 #else  // dispatch object
 
-static const int kDepthsF32[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 16};
+static const int kDepthsF32[] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 11, 12, 13, 14, 16};
 static const int kDepthsF64[] = {1, 2, 3, 4};
 
 int march2d_depths(int dtype, const int **list) {
@@ -640,7 +640,7 @@ int march2d_depths(int dtype, const int **list) {
     return (int)(sizeof(kDepthsF64) / sizeof(int));
 }
 
-// Calls F<R, depth>(args...) for a compiled depth (1..8, 10, 12, 16 in FP32,
+// Calls F<R, depth>(args...) for a compiled depth (1..8, 10..14, 16 in FP32,
 // 1..4 in FP64); `bad` otherwise.
 #define JAC_M2_CASE(F, R, D, BAD, ...)                                  \
     case D:                                                             \
@@ -659,7 +659,10 @@ int march2d_depths(int dtype, const int **list) {
         JAC_M2_CASE(F, R, 7, BAD, __VA_ARGS__)                          \
         JAC_M2_CASE(F, R, 8, BAD, __VA_ARGS__)                          \
         JAC_M2_CASE(F, R, 10, BAD, __VA_ARGS__)                         \
+        JAC_M2_CASE(F, R, 11, BAD, __VA_ARGS__)                         \
         JAC_M2_CASE(F, R, 12, BAD, __VA_ARGS__)                         \
+        JAC_M2_CASE(F, R, 13, BAD, __VA_ARGS__)                         \
+        JAC_M2_CASE(F, R, 14, BAD, __VA_ARGS__)                         \
         JAC_M2_CASE(F, R, 16, BAD, __VA_ARGS__)                         \
     default:                                                            \
         return BAD;                                                     \
