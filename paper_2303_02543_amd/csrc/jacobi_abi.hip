@@ -790,7 +790,7 @@ int jacobi_autotune(jacobi_t h, int64_t n_sweeps, int with_source, int *t_depth,
         std::vector<Cand> cands;
         cands.push_back({1, 0, JACOBI_FLAG_EXPLICIT_HALO});
         if (h->g.ndim == 2)
-            for (int rg : {1, 2, 4, 8}) cands.push_back({1, rg, JACOBI_FLAG_EXPLICIT_HALO});
+            for (int rg : {2, 4, 8, 16}) cands.push_back({1, rg, JACOBI_FLAG_EXPLICIT_HALO});
         if (h->g.ndim == 3) {
             static const int kZseg[] = {8, 16, 32, 64, 128};
             for (int z : kZseg)

@@ -13,13 +13,13 @@
 // filled), the step order of the paper's proxy -- exchange, then update.  The
 // fused multi-sweep pass kernel lives in k_march2d.hip.
 //
-// 2D blocks use k_sweep_rows: a wave owns 64 lanes x V columns of one block
-// and walks down a short group of rows, keeping the rows above and below in
-// registers and taking west/east neighbours from the adjacent lanes (DPP).
-// Work items are numbered in memory order (column chunk, then row group,
-// then block), so the waves resident at any time stream one compact window
-// of the arrays, the access pattern HBM serves best.  3D blocks use
-// k_sweep_local.
+// 2D blocks use k_sweep_tile (a workgroup walks a tile of rows 4 at a time,
+// sharing rows through LDS) or, for 1-3 rows per work item, k_sweep_rows (a
+// wave walks a short group of rows, keeping the rows above and below in
+// registers).  Both take west/east neighbours from the adjacent lanes (DPP)
+// and number work items in memory order (column chunk, then rows, then
+// block), so the waves resident at any time stream one compact window of the
+// arrays, the access pattern HBM serves best.  3D blocks use k_sweep_local.
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
@@ -184,10 +184,109 @@ __global__ __launch_bounds__(256) void k_sweep_rows(Geom g, const R *__restrict_
     }
 }
 
-// Rows per work item of k_sweep_rows when none is given: the fastest
-// measured on MI355X for 8192^2 FP32 / FP64 (a row group shares its two
-// boundary rows with its neighbours; longer groups stream worse).
-template <typename R> constexpr int sweep_rows_default() { return sizeof(R) == 4 ? 2 : 4; }
+// ------------------------------------------------------- tile sweep (2D)
+// A workgroup of 4 waves owns one 64 x V column chunk of a block and a tile
+// of 4 * steps rows, and walks down it 4 rows per step (wave q takes row
+// Y + q).  Each row is loaded from memory once: the waves put their rows in
+// LDS and take the rows above and below from there; wave 3 also loads the
+// row after the step's 4 rows, and wave 0 takes the row before them from the
+// previous step's buffer.  Three LDS buffers by step make one barrier per
+// step enough: a wave is at most one step ahead of the others, so a buffer
+// being written is never one still being read.
+template <typename R, bool SRC>
+__global__ __launch_bounds__(256) void k_sweep_tile(Geom g, const R *__restrict__ uin,
+                                                    R *__restrict__ uout,
+                                                    const R *__restrict__ b, int steps,
+                                                    int ntiles, int nchunks, int nitems) {
+    constexpr int V = 16 / sizeof(R);
+    constexpr int W = 64 * V;
+    using C = Chunk<R, V>;
+    __shared__ C sh[3][6][64];  // slots 1..4: the step's rows, 5: the row after
+    const int item = blockIdx.x;  // memory order, as in k_sweep_rows
+    if (item >= nitems) return;   // whole workgroup
+    const int chunk = item % nchunks;
+    const int rest = item / nchunks;
+    const int tile = rest % ntiles;
+    const int blk = rest / ntiles;
+    const int bx = blk % g.nb[0], by = blk / g.nb[0];
+    const int ex = extent(g.n[0], g.e[0], bx);
+    const int ey = extent(g.n[1], g.e[1], by);
+    const int y0 = tile * 4 * steps;
+    if (y0 >= ey) return;  // tile beyond a short block (whole workgroup)
+    const int nst = ((ey - y0 < 4 * steps ? ey - y0 : 4 * steps) + 3) / 4;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = chunk * W + lane * V;
+    const bool ld = c <= ex;
+    const int xe = lane == 0 ? c - 1 : lane == 63 ? c + V : c;
+    const bool lde = xe <= ex && (lane == 0 || lane == 63 || ld);
+    // byte offsets from the start of a stored row (non-negative)
+    const R *base = uin + (int64_t)blk * g.bstride;
+    const uint32_t lane_b = (uint32_t)((g.ax + (ld ? c : 0)) * (int)sizeof(R));
+    const uint32_t edge_b = (uint32_t)((g.ax + (lde ? xe : 0)) * (int)sizeof(R));
+    bool upd[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) upd[v] = c + v < ex;
+    const bool full = c + V <= ex;
+    auto row_of = [&](int ly) { return base + (int64_t)(ly + 1) * g.pitch; };
+    auto load = [&](int ly) {
+        C r = at<C>(row_of(ly), lane_b);
+        if (!ld) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) r.v[v] = (R)0;
+        }
+        return r;
+    };
+    const R *bsrc = SRC ? b + (int64_t)blk * g.sstride : nullptr;
+    const R w = (R)0.25;
+    if (wv == 0) sh[2][4][lane] = load(y0 - 1);  // "previous step's last row"
+    for (int s = 0; s < nst; ++s) {
+        const int buf = s % 3, prev = (s + 2) % 3;
+        const int y = y0 + 4 * s + wv;
+        const bool valid = y < ey;      // wave-uniform
+        const int yl = valid ? y : ey;  // rows past the block read the ring row
+        const C cen = load(yl);
+        sh[buf][wv + 1][lane] = cen;
+        if (wv == 3) sh[buf][5][lane] = load(y + 1 < ey ? y + 1 : ey);
+        const R e = at<R>(row_of(yl), edge_b);
+        C bb;
+        if constexpr (SRC) {
+            bb = at<C>(bsrc + (int64_t)(valid ? y : 0) * g.e[0],
+                       (uint32_t)((ld && c < ex ? c : 0) * (int)sizeof(R)));
+        }
+        __syncthreads();
+        const C up = wv == 0 ? sh[prev][4][lane] : sh[buf][wv][lane];
+        const C dn = sh[buf][wv + 2][lane];
+        const R eo = lde ? e : (R)0;
+        const R left = shift_up(eo, cen.v[V - 1]);
+        const R right = shift_down(eo, cen.v[0]);
+        C out;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const R Wv = v > 0 ? cen.v[v - 1] : left;
+            const R Ev = v < V - 1 ? cen.v[v + 1] : right;
+            const R sum = (Wv + Ev) + (up.v[v] + dn.v[v]);
+            out.v[v] = SRC ? (sum + bb.v[v]) * w : sum * w;
+        }
+        if (valid) {
+            R *orow = uout + (int64_t)blk * g.bstride + (int64_t)(y + 1) * g.pitch;
+            if (full) {
+                at_mut<C>(orow, lane_b) = out;
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if (upd[v]) orow[g.ax + c + v] = out.v[v];
+            }
+        }
+    }
+}
+
+// Rows per work item of the 2D block-local sweep when none is given (fastest
+// measured on MI355X for 8192^2 FP32 / FP64).  Below 4, k_sweep_rows runs
+// that many rows per wave; from 4 on, k_sweep_tile runs tiles of that many
+// rows (rounded up to a multiple of 4).
+// (4: one 4-row step per workgroup; taller tiles read fewer boundary rows but
+// stream worse).
+template <typename R> constexpr int sweep_rows_default() { return 4; }
 
 template <typename R>
 static hipError_t launch_sweep_rows(const Geom &g, const void *uin, void *uout, const void *b,
@@ -195,6 +294,21 @@ static hipError_t launch_sweep_rows(const Geom &g, const void *uin, void *uout, 
     constexpr int W = 64 * (16 / (int)sizeof(R));
     if (rg <= 0) rg = sweep_rows_default<R>();
     const int nchunks = (g.e[0] + W - 1) / W;
+    if (rg >= 4) {
+        const int steps = (rg + 3) / 4;
+        const int ntiles = (g.e[1] + 4 * steps - 1) / (4 * steps);
+        const int64_t items = (int64_t)g.nblocks * ntiles * nchunks;
+        if (items > 0x7fffffff) return hipErrorInvalidValue;
+        if (b)
+            hipLaunchKernelGGL((k_sweep_tile<R, true>), dim3((unsigned)items), dim3(256), 0, st, g,
+                               (const R *)uin, (R *)uout, (const R *)b, steps, ntiles, nchunks,
+                               (int)items);
+        else
+            hipLaunchKernelGGL((k_sweep_tile<R, false>), dim3((unsigned)items), dim3(256), 0, st,
+                               g, (const R *)uin, (R *)uout, (const R *)nullptr, steps, ntiles,
+                               nchunks, (int)items);
+        return hipGetLastError();
+    }
     const int ngroups = (g.e[1] + rg - 1) / rg;
     const int64_t nwork = (int64_t)g.nblocks * ngroups * nchunks;
     if (nwork > 0x7fffffff - 3) return hipErrorInvalidValue;

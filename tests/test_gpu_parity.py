@@ -81,7 +81,7 @@ def test_2d_bit_exact_all_depths(device, dtype, case):
     for fl in (0, jb.JACOBI_FLAG_DEEP_PREFETCH):
         got, _ = run_device(U0, None, h2, K, (bx, by), dtype, device, depth=depths[-1], flags=fl)
         assert_bits(got, want_l, "2d laplace %s flags %d" % (case, fl))
-    for rg in (0, 1, 3, 64):
+    for rg in (0, 1, 3, 5, 64):
         # explicit exchange + block-local sweep; rows = rows per work item
         got, _ = run_device(U0, f, h2, K, (bx, by), dtype, device, rows=rg,
                             flags=jb.JACOBI_FLAG_EXPLICIT_HALO)
