@@ -307,9 +307,13 @@ def cpu_baseline(U0_np, f_np, h2, target_seconds, full_max_seconds, gpu_final):
     U = U0_np.astype(np.float64)
     b = oracle.scale_source(f_np.astype(np.float64), h2, np.float64)
     oracle.sweep(U, b, 1)  # untimed: thread start-up, first touch of the arrays
+    # per-sweep time from two run lengths (each call also copies the grid)
     t0 = time.perf_counter()
     oracle.sweep(U, b, 2)
-    per_sweep = (time.perf_counter() - t0) / 2
+    t2 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.sweep(U, b, 12)
+    per_sweep = max((time.perf_counter() - t0 - t2) / 10, 1e-6)
     cells = float(N) * N
     out = {"unit": "GLUP/s", "cores": oracle.num_threads(), "kind": "oracle"}
     if per_sweep * SWEEPS <= full_max_seconds:
