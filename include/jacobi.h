@@ -74,7 +74,14 @@ enum jacobi_flags {
     /* 2D passes load rows three steps ahead of their use instead of one
      * (more bytes in flight per wave, more registers per wave).  A pure
      * performance choice; results are identical either way. */
-    JACOBI_FLAG_DEEP_PREFETCH = 4
+    JACOBI_FLAG_DEEP_PREFETCH = 4,
+    /* With JACOBI_FLAG_EXPLICIT_HALO (required): cut the blocks into up to 4
+     * slabs of block layers along the slowest axis and overlap each slab's
+     * face sends (on a second stream the library owns, default priority)
+     * with the sweep of the next slab -- the over-decomposition of Section
+     * 4.4, one piece's halo transfer hidden under another piece's kernel.
+     * Results are identical to the explicit-halo schedule. */
+    JACOBI_FLAG_OVERLAP = 8
 };
 
 /* ---------------------------------------------------------------- set-up */

@@ -21,6 +21,7 @@ JACOBI_F64 = 1
 JACOBI_FLAG_EXPLICIT_HALO = 1
 JACOBI_FLAG_NT_STORES = 2
 JACOBI_FLAG_DEEP_PREFETCH = 4
+JACOBI_FLAG_OVERLAP = 8
 
 JACOBI_RUNNING = 0
 JACOBI_CONVERGED = 1

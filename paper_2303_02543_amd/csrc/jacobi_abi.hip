@@ -151,6 +151,9 @@ int plan(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, Geom *
 
 }  // namespace
 
+// Pieces of an overlapped explicit-halo sweep (slabs of block layers).
+constexpr int kPieces = 4;
+
 struct jacobi_s {
     Geom g;
     Layout lay;
@@ -174,6 +177,11 @@ struct jacobi_s {
         double updates, bytes;
     };
     std::vector<Rec> recs;  // one per recorded launch; events 2i, 2i+1
+    // overlapped explicit-halo sweeps: the stream that sends faces, and
+    // events handing each piece over to it and joining it back
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_piece[kPieces] = {};
+    hipEvent_t ev_join = nullptr;
 };
 
 namespace {
@@ -308,6 +316,56 @@ int do_residual(jacobi_t h, double *out) {
     return JACOBI_OK;
 }
 
+// Explicit-halo sweeps with the exchange overlapped: the blocks are cut into
+// up to kPieces slabs of whole block layers along the slowest axis; each
+// slab is swept on the handle's stream, then its faces are sent into its
+// neighbours' halos of the new state on a second stream while the next slab
+// is swept (the over-decomposition of Section 4.4: one piece's transfer
+// hidden under another piece's kernel).  The sweeps read the old state and
+// write only interiors of the new one, the sends write only halos of the new
+// state, so the two streams never touch the same elements; the handle's
+// stream waits for all sends before the next sweep.
+template <typename R>
+int do_sweep_overlap(jacobi_t h, int64_t n, double *res_first) {
+    const void *b = h->has_source ? h->b : nullptr;
+    if (res_first) {
+        int rc = do_residual<R>(h, res_first);
+        if (rc) return rc;
+    }
+    if (n == 0) return JACOBI_OK;
+    if (!h->stream2) {
+        HIP_TRY(hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking), "stream create");
+        for (hipEvent_t &ev : h->ev_piece)
+            HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event create");
+        HIP_TRY(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming), "event create");
+    }
+    const int slow = h->g.ndim - 1;
+    const int64_t layers = h->g.nb[slow];
+    const int64_t per_layer = h->g.nblocks / layers;
+    const int pieces = layers < kPieces ? (int)layers : kPieces;
+    for (int64_t k = 0; k < n; ++k) {
+        int rc = prof_begin(h);
+        if (rc) return rc;
+        for (int p = 0; p < pieces; ++p) {
+            const int64_t b0 = layers * p / pieces * per_layer;
+            const int64_t b1 = layers * (p + 1) / pieces * per_layer;
+            HIP_TRY(jac::launch_sweep_local<R>(h->g, h->u[h->cur], h->u[h->cur ^ 1], b, h->stream,
+                                               h->rows, b0, b1),
+                    "sweep launch");
+            HIP_TRY(hipEventRecord(h->ev_piece[p], h->stream), "event record");
+            HIP_TRY(hipStreamWaitEvent(h->stream2, h->ev_piece[p], 0), "stream wait");
+            HIP_TRY(jac::launch_halo_send<R>(h->g, h->u[h->cur ^ 1], b0, b1, h->stream2),
+                    "halo send launch");
+        }
+        HIP_TRY(hipEventRecord(h->ev_join, h->stream2), "event record");
+        HIP_TRY(hipStreamWaitEvent(h->stream, h->ev_join, 0), "stream wait");
+        rc = prof_end(h, 1);
+        if (rc) return rc;
+        h->cur ^= 1;
+    }
+    return JACOBI_OK;
+}
+
 // n sweeps; if res_first is not NULL, the FP64 residual of the state the call
 // starts from is written there (folded into the first pass when possible).
 template <typename R>
@@ -338,6 +396,7 @@ int do_sweep(jacobi_t h, int64_t n, double *res_first) {
         HIP_TRY(jac::launch_halo_exchange<R>(h->g, h->u[h->cur], h->stream), "halo exchange launch");
         return JACOBI_OK;
     }
+    if ((h->flags & JACOBI_FLAG_OVERLAP) && explicit_halo) return do_sweep_overlap<R>(h, n, res_first);
     if (explicit_halo || n == 0) {
         if (res_first) {
             int rc = do_residual<R>(h, res_first);
@@ -482,6 +541,14 @@ int jacobi_create(int ndim, const int64_t *grid, const int64_t *blocks, int dtyp
 int jacobi_destroy(jacobi_t h) {
     if (!h) return JACOBI_OK;
     hipError_t e = hipStreamSynchronize(h->stream);
+    if (h->stream2) {
+        const hipError_t e2 = hipStreamSynchronize(h->stream2);
+        if (e == hipSuccess) e = e2;
+        hipStreamDestroy(h->stream2);
+    }
+    for (hipEvent_t ev : h->ev_piece)
+        if (ev) hipEventDestroy(ev);
+    if (h->ev_join) hipEventDestroy(h->ev_join);
     for (hipEvent_t ev : h->ev_pool) hipEventDestroy(ev);
     delete h;
     if (e != hipSuccess) return hip_fail(e, "stream synchronize in destroy");
@@ -674,8 +741,11 @@ int jacobi_set_tuning(jacobi_t h, int t_depth, int rows, int flags) {
         ((flags & JACOBI_FLAG_EXPLICIT_HALO) && h->g.ndim == 2) ? 1 : kMinRows;
     if (rows < 0 || (rows > 0 && rows < min_rows) || rows > (1 << 20))
         return fail(JACOBI_E_INVAL, "rows must be 0 or in [%d, 2^20] (got %d)", min_rows, rows);
-    if (flags & ~(JACOBI_FLAG_EXPLICIT_HALO | JACOBI_FLAG_NT_STORES | JACOBI_FLAG_DEEP_PREFETCH))
+    if (flags & ~(JACOBI_FLAG_EXPLICIT_HALO | JACOBI_FLAG_NT_STORES | JACOBI_FLAG_DEEP_PREFETCH |
+                  JACOBI_FLAG_OVERLAP))
         return fail(JACOBI_E_INVAL, "unknown flags 0x%x", flags);
+    if ((flags & JACOBI_FLAG_OVERLAP) && !(flags & JACOBI_FLAG_EXPLICIT_HALO))
+        return fail(JACOBI_E_INVAL, "JACOBI_FLAG_OVERLAP needs JACOBI_FLAG_EXPLICIT_HALO");
     h->depth = t_depth;
     h->rows = rows;
     h->flags = flags;
@@ -791,6 +861,7 @@ int jacobi_autotune(jacobi_t h, int64_t n_sweeps, int with_source, int *t_depth,
         cands.push_back({1, 0, JACOBI_FLAG_EXPLICIT_HALO});
         if (h->g.ndim == 2)
             for (int rg : {2, 4, 8, 16}) cands.push_back({1, rg, JACOBI_FLAG_EXPLICIT_HALO});
+        cands.push_back({1, 0, JACOBI_FLAG_EXPLICIT_HALO | JACOBI_FLAG_OVERLAP});
         if (h->g.ndim == 3) {
             static const int kZseg[] = {8, 16, 32, 64, 128};
             for (int z : kZseg)

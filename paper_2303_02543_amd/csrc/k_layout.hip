@@ -109,6 +109,49 @@ __global__ __launch_bounds__(256) void k_halo_exchange(Geom g, R *__restrict__ s
     }
 }
 
+// Face sends of the source blocks b0 .. b1-1: work item (block, face, t) as
+// in k_halo_exchange, but the block is the sender: its edge cells go into
+// the halo of its face neighbour.  Sending the faces of every block fills
+// the same halo cells, with the same values, as k_halo_exchange.
+template <typename R>
+__global__ __launch_bounds__(256) void k_halo_send(Geom g, R *__restrict__ s, int64_t b0,
+                                                   int64_t maxface, int64_t total) {
+    const int nf = 2 * g.ndim;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = i % maxface;
+        const int64_t rest = i / maxface;
+        const int face = (int)(rest % nf);
+        const int64_t blk = b0 + rest / nf;
+        const int axis = face >> 1, side = face & 1;
+        int bc[3];
+        bc[0] = (int)(blk % g.nb[0]);
+        bc[1] = (int)((blk / g.nb[0]) % g.nb[1]);
+        bc[2] = (int)(blk / ((int64_t)g.nb[0] * g.nb[1]));
+        if (side == 0 && bc[axis] == 0) continue;
+        if (side == 1 && bc[axis] == g.nb[axis] - 1) continue;
+        int ext[3];
+        for (int a = 0; a < 3; ++a) ext[a] = a < g.ndim ? extent(g.n[a], g.e[a], bc[a]) : 1;
+        const int ta = axis == 0 ? 1 : 0;
+        const int tb = axis == 2 ? 1 : 2;
+        const int64_t fa = ext[ta];
+        const int64_t fb = (g.ndim == 3) ? ext[tb] : 1;
+        if (t >= fa * fb) continue;
+        int loc[3] = {0, 0, 0};
+        loc[ta] = (int)(t % fa);
+        if (g.ndim == 3) loc[tb] = (int)(t / fa);
+        loc[axis] = side == 0 ? 0 : ext[axis] - 1;  // the block's edge cell
+        const int64_t src = local_offset(g, blk, loc[0], loc[1], loc[2]);
+        // the neighbour across the face and the halo slot facing this block
+        int64_t step = 1;
+        for (int a = 0; a < axis; ++a) step *= g.nb[a];
+        const int64_t nbr = side == 0 ? blk - step : blk + step;
+        int nloc[3] = {loc[0], loc[1], loc[2]};
+        nloc[axis] = side == 0 ? g.e[axis] : -1;  // a low neighbour is a full block
+        s[local_offset(g, nbr, nloc[0], nloc[1], nloc[2])] = s[src];
+    }
+}
+
 static inline int grid_for(int64_t total) {
     int64_t b = (total + 255) / 256;
     if (b > 65536) b = 65536;
@@ -213,6 +256,18 @@ hipError_t launch_halo_exchange(const Geom &g, void *s, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_halo_send(const Geom &g, void *s, int64_t b0, int64_t b1, hipStream_t st) {
+    const int64_t maxface = halo_maxface(g);
+    const int64_t total = (b1 - b0) * 2 * g.ndim * maxface;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_halo_send<R>, dim3(grid_for(total)), dim3(256), 0, st, g, (R *)s, b0,
+                       maxface, total);
+    return hipGetLastError();
+}
+
+template hipError_t launch_halo_send<float>(const Geom &, void *, int64_t, int64_t, hipStream_t);
+template hipError_t launch_halo_send<double>(const Geom &, void *, int64_t, int64_t, hipStream_t);
 template hipError_t launch_scatter<float>(const Geom &, const void *, void *, void *, bool,
                                           hipStream_t);
 template hipError_t launch_scatter<double>(const Geom &, const void *, void *, void *, bool,

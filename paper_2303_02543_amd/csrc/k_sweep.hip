@@ -37,7 +37,8 @@ template <typename R> __device__ __forceinline__ R weight2d() { return (R)0.25; 
 template <typename R, bool SRC>
 __global__ __launch_bounds__(256) void k_sweep_local(Geom g, const R *__restrict__ uin,
                                                      R *__restrict__ uout,
-                                                     const R *__restrict__ b, int64_t total) {
+                                                     const R *__restrict__ b, int64_t blk0,
+                                                     int64_t total) {
     constexpr int V = 16 / sizeof(R);
     const int cpr = (g.e[0] + V - 1) / V;           // chunks per row
     const int64_t rows = (int64_t)g.e[1] * (g.ndim == 3 ? g.e[2] : 1);
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(256) void k_sweep_local(Geom g, const R *__restrict
     const int cx = (int)(i % cpr);
     const int64_t rest = i / cpr;
     const int64_t rr = rest % rows;
-    const int64_t blk = rest / rows;
+    const int64_t blk = blk0 + rest / rows;
     const int ly = (int)(rr % g.e[1]);
     const int lz = (int)(rr / g.e[1]);
     const int bx = (int)(blk % g.nb[0]);
@@ -102,7 +103,7 @@ template <typename R, bool SRC>
 __global__ __launch_bounds__(256) void k_sweep_rows(Geom g, const R *__restrict__ uin,
                                                     R *__restrict__ uout,
                                                     const R *__restrict__ b, int rg, int ngroups,
-                                                    int nchunks, int nwork) {
+                                                    int nchunks, int blk0, int nwork) {
     constexpr int V = 16 / sizeof(R);
     constexpr int W = 64 * V;
     using C = Chunk<R, V>;
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows(Geom g, const R *__restrict_
     const int chunk = wid % nchunks;
     const int rest = wid / nchunks;
     const int grp = rest % ngroups;
-    const int blk = rest / ngroups;
+    const int blk = blk0 + rest / ngroups;
     const int bx = blk % g.nb[0], by = blk / g.nb[0];
     const int ex = extent(g.n[0], g.e[0], bx);
     const int ey = extent(g.n[1], g.e[1], by);
@@ -197,7 +198,8 @@ template <typename R, bool SRC>
 __global__ __launch_bounds__(256) void k_sweep_tile(Geom g, const R *__restrict__ uin,
                                                     R *__restrict__ uout,
                                                     const R *__restrict__ b, int steps,
-                                                    int ntiles, int nchunks, int nitems) {
+                                                    int ntiles, int nchunks, int blk0,
+                                                    int nitems) {
     constexpr int V = 16 / sizeof(R);
     constexpr int W = 64 * V;
     using C = Chunk<R, V>;
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(256) void k_sweep_tile(Geom g, const R *__restrict_
     const int chunk = item % nchunks;
     const int rest = item / nchunks;
     const int tile = rest % ntiles;
-    const int blk = rest / ntiles;
+    const int blk = blk0 + rest / ntiles;
     const int bx = blk % g.nb[0], by = blk / g.nb[0];
     const int ex = extent(g.n[0], g.e[0], bx);
     const int ey = extent(g.n[1], g.e[1], by);
@@ -290,61 +292,63 @@ template <typename R> constexpr int sweep_rows_default() { return 4; }
 
 template <typename R>
 static hipError_t launch_sweep_rows(const Geom &g, const void *uin, void *uout, const void *b,
-                                    int rg, hipStream_t st) {
+                                    int rg, int64_t b0, int64_t b1, hipStream_t st) {
     constexpr int W = 64 * (16 / (int)sizeof(R));
     if (rg <= 0) rg = sweep_rows_default<R>();
     const int nchunks = (g.e[0] + W - 1) / W;
     if (rg >= 4) {
         const int steps = (rg + 3) / 4;
         const int ntiles = (g.e[1] + 4 * steps - 1) / (4 * steps);
-        const int64_t items = (int64_t)g.nblocks * ntiles * nchunks;
+        const int64_t items = (b1 - b0) * ntiles * nchunks;
         if (items > 0x7fffffff) return hipErrorInvalidValue;
         if (b)
             hipLaunchKernelGGL((k_sweep_tile<R, true>), dim3((unsigned)items), dim3(256), 0, st, g,
                                (const R *)uin, (R *)uout, (const R *)b, steps, ntiles, nchunks,
-                               (int)items);
+                               (int)b0, (int)items);
         else
             hipLaunchKernelGGL((k_sweep_tile<R, false>), dim3((unsigned)items), dim3(256), 0, st,
                                g, (const R *)uin, (R *)uout, (const R *)nullptr, steps, ntiles,
-                               nchunks, (int)items);
+                               nchunks, (int)b0, (int)items);
         return hipGetLastError();
     }
     const int ngroups = (g.e[1] + rg - 1) / rg;
-    const int64_t nwork = (int64_t)g.nblocks * ngroups * nchunks;
+    const int64_t nwork = (b1 - b0) * ngroups * nchunks;
     if (nwork > 0x7fffffff - 3) return hipErrorInvalidValue;
     const int grid = (int)((nwork + 3) / 4);
     if (b)
         hipLaunchKernelGGL((k_sweep_rows<R, true>), dim3(grid), dim3(256), 0, st, g,
                            (const R *)uin, (R *)uout, (const R *)b, rg, ngroups, nchunks,
-                           (int)nwork);
+                           (int)b0, (int)nwork);
     else
         hipLaunchKernelGGL((k_sweep_rows<R, false>), dim3(grid), dim3(256), 0, st, g,
                            (const R *)uin, (R *)uout, (const R *)nullptr, rg, ngroups, nchunks,
-                           (int)nwork);
+                           (int)b0, (int)nwork);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_sweep_local(const Geom &g, const void *uin, void *uout, const void *b,
-                              hipStream_t st, int rg) {
-    if (g.ndim == 2) return launch_sweep_rows<R>(g, uin, uout, b, rg, st);
+                              hipStream_t st, int rg, int64_t b0, int64_t b1) {
+    if (b1 < 0) b1 = g.nblocks;
+    if (b0 < 0 || b1 > g.nblocks || b0 >= b1) return b0 == b1 ? hipSuccess : hipErrorInvalidValue;
+    if (g.ndim == 2) return launch_sweep_rows<R>(g, uin, uout, b, rg, b0, b1, st);
     constexpr int V = 16 / sizeof(R);
     const int64_t cpr = (g.e[0] + V - 1) / V;
-    const int64_t total = g.nblocks * (int64_t)g.e[1] * (g.ndim == 3 ? g.e[2] : 1) * cpr;
+    const int64_t total = (b1 - b0) * (int64_t)g.e[1] * (g.ndim == 3 ? g.e[2] : 1) * cpr;
     const int64_t grid = (total + 255) / 256;
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
     if (b)
         hipLaunchKernelGGL((k_sweep_local<R, true>), dim3((unsigned)grid), dim3(256), 0, st, g,
-                           (const R *)uin, (R *)uout, (const R *)b, total);
+                           (const R *)uin, (R *)uout, (const R *)b, b0, total);
     else
         hipLaunchKernelGGL((k_sweep_local<R, false>), dim3((unsigned)grid), dim3(256), 0, st, g,
-                           (const R *)uin, (R *)uout, (const R *)nullptr, total);
+                           (const R *)uin, (R *)uout, (const R *)nullptr, b0, total);
     return hipGetLastError();
 }
 
 template hipError_t launch_sweep_local<float>(const Geom &, const void *, void *, const void *,
-                                              hipStream_t, int);
+                                              hipStream_t, int, int64_t, int64_t);
 template hipError_t launch_sweep_local<double>(const Geom &, const void *, void *, const void *,
-                                               hipStream_t, int);
+                                               hipStream_t, int, int64_t, int64_t);
 
 }  // namespace jac

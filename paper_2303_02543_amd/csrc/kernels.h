@@ -21,11 +21,15 @@ hipError_t launch_scale_source(const Geom &g, const void *f, void *b, double h2,
 template <typename R>
 hipError_t launch_halo_exchange(const Geom &g, void *s, hipStream_t st);
 
-// One sweep of every block from its own storage (halos must be current).
-// 2D: rg rows per work item (0: a default).
+// One sweep of blocks b0 .. b1-1 (b1 < 0: to the last block) from their own
+// storage (halos must be current).  2D: rg rows per work item (0: a default).
 template <typename R>
 hipError_t launch_sweep_local(const Geom &g, const void *uin, void *uout, const void *b,
-                              hipStream_t st, int rg = 0);
+                              hipStream_t st, int rg = 0, int64_t b0 = 0, int64_t b1 = -1);
+// Face sends of blocks b0 .. b1-1: each block's edge cells into the halos of
+// its face neighbours (all blocks together: the same as launch_halo_exchange).
+template <typename R>
+hipError_t launch_halo_send(const Geom &g, void *s, int64_t b0, int64_t b1, hipStream_t st);
 
 // `depth` sweeps in one pass over the whole 2D grid, reading face neighbours'
 // cells from their owning blocks.  uout may be NULL (no output: residual

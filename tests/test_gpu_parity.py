@@ -31,7 +31,7 @@ def assert_bits(got, want, what):
 
 
 # ------------------------------------------------------------------ config 1
-@pytest.mark.parametrize("depth,flags", [(1, 0), (2, 0), (3, 0), (4, 0), (1, 1)])
+@pytest.mark.parametrize("depth,flags", [(1, 0), (2, 0), (3, 0), (4, 0), (1, 1), (1, 9)])
 def test_config1_bit_exact(device, depth, flags):
     """2D Laplace 256^2 FP64, 2x2 blocks of 128^2, 100 sweeps, residual every 10:
     bit-exact with the monolithic oracle; residuals within 1e-12."""
@@ -89,6 +89,11 @@ def test_2d_bit_exact_all_depths(device, dtype, case):
     got, _ = run_device(U0, None, h2, K, (bx, by), dtype, device, rows=3,
                         flags=jb.JACOBI_FLAG_EXPLICIT_HALO)
     assert_bits(got, want_l, "2d explicit halo laplace %s" % (case,))
+    for rg in (0, 3):
+        # slabs swept and their faces sent on a second stream, overlapped
+        got, _ = run_device(U0, f, h2, K, (bx, by), dtype, device, rows=rg,
+                            flags=jb.JACOBI_FLAG_EXPLICIT_HALO | jb.JACOBI_FLAG_OVERLAP)
+        assert_bits(got, want, "2d overlapped explicit halo %s rows %d" % (case, rg))
     got, _ = run_device(U0, f, h2, K, (bx, by), dtype, device, depth=depths[-1],
                         flags=jb.JACOBI_FLAG_NT_STORES)
     assert_bits(got, want, "2d non-temporal stores %s" % (case,))
@@ -139,7 +144,8 @@ def test_3d_bit_exact(device, dtype, case):
     import paper_2303_02543_amd as jb
     want, _ = oracle_run(U0, f, h2, K, dtype)
     for rows, flags in ((0, 0), (8, 0), (64, 0), (0, jb.JACOBI_FLAG_EXPLICIT_HALO),
-                        (16, jb.JACOBI_FLAG_NT_STORES)):
+                        (16, jb.JACOBI_FLAG_NT_STORES),
+                        (0, jb.JACOBI_FLAG_EXPLICIT_HALO | jb.JACOBI_FLAG_OVERLAP)):
         got, res = run_device(U0, f, h2, K, (bx, by, bz), dtype, device, rows=rows, flags=flags,
                               check_every=3)
         assert_bits(got, want, "3d %s rows %d flags %d" % (case, rows, flags))
@@ -248,6 +254,11 @@ def test_errors_on_device(device):
         s.sweep(0)
         with pytest.raises(jb.JacobiError):
             s.set_tuning(99, 0, 0)
+        with pytest.raises(jb.JacobiError) as ei:
+            s.set_tuning(1, 0, jb.JACOBI_FLAG_OVERLAP)  # needs the explicit-halo flag
+        assert ei.value.status == jb.JACOBI_E_INVAL
+        with pytest.raises(jb.JacobiError):
+            s.set_tuning(1, 0, 64)  # unknown flag bit
         with pytest.raises(jb.JacobiError):
             s.set_source(torch.zeros((16, 16), dtype=torch.float64, device=device), -1.0)
         assert s.residual() == 0.0
