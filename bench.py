@@ -309,6 +309,42 @@ def bench_overdecomposition():
             "points": rows}
 
 
+def bench_paper_domain():
+    """The paper's Jacobi3D domain (Section 4.3), 1024 x 1024 x 768, 7-point
+    Poisson in 16 x 16 x 12 blocks of 64^3, a fixed number of sweeps as in the
+    paper (no residual), FP32 and FP64, autotuned 3D schedule."""
+    import numpy as np
+    import torch
+    import paper_2303_02543_amd as jb
+    import synthetic
+    dev = torch.device("cuda:0")
+    nx, ny, nz, K = 1024, 1024, 768, 40
+    out = {"workload": "3D 7-point Poisson %dx%dx%d (the paper's Jacobi3D domain), 16x16x12 "
+                       "blocks of 64^3, %d sweeps" % (nx, ny, nz, K)}
+    tile = synthetic.uniform((48, 64, 64), 13, -1.0, 1.0)
+    for name, np_dt, t_dt in (("f32", np.float32, torch.float32), ("f64", np.float64, torch.float64)):
+        s = jb.Solver((nx, ny, nz), (16, 16, 12), t_dt, device=dev)
+        try:
+            s.autotune(10, with_source=True)
+            s.set_source(torch.from_numpy(np.tile(tile.astype(np_dt), (16, 16, 16))).to(dev),
+                         synthetic.spacing2(nx))
+            s.set_state(torch.zeros((nz + 2, ny + 2, nx + 2), dtype=t_dt, device=dev))
+            s.sweep(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.sweep(K)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            es = 4 if name == "f32" else 8
+            glups = float(nx) * ny * nz * K / dt / 1e9
+            d3, z3, f3 = s.get_tuning()
+            out[name] = {"glups": round(glups, 2), "hbm_gbs_alg": round(glups * 3 * es, 1),
+                         "zseg": z3, "flags": f3}
+        finally:
+            s.close()
+    return out
+
+
 def source_hash(path):
     with open(path, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
@@ -525,6 +561,7 @@ def main():
         out["poisson3d"] = bench_poisson3d(glups)
         out["plain2d"] = bench_plain2d()
         out["overdecomposition"] = bench_overdecomposition()
+        out["paper_domain_3d"] = bench_paper_domain()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(U0_np, f32, h2, args.cpu_seconds,
                                            args.cpu_full_seconds, U_out.cpu().numpy())
