@@ -213,12 +213,13 @@ int balanced_rows(const jacobi_s *h, int depth, int mode, int rounds, int deep) 
     return (int)rows;
 }
 
-// Defaults before any tuning: the fastest depth measured on MI355X for a 2D
-// FP32 8192^2 grid, with a tile height that fills the GPU in one round;
-// explicit halos (depth 1) for 3D.
+// Defaults before any tuning: the fastest schedule measured on MI355X for a
+// 2D FP32 8192^2 grid with a residual every 50 sweeps (depth 13: passes of
+// 13, 13, 12, 12), with a tile height that fills the GPU in one round of
+// resident waves; one sweep per pass in 3D.
 int default_depth(const jacobi_s *h) {
     if (h->g.ndim == 3) return 1;
-    return h->dtype == JACOBI_F32 ? 12 : 4;
+    return h->dtype == JACOBI_F32 ? 13 : 4;
 }
 
 // The 2D pass kernels address a lane's chunk as a 32-bit byte offset from a
