@@ -145,7 +145,7 @@ def bench_adjoint(plain_glups):
     from paper_2303_02543_amd.autograd import JacobiK
     dev = torch.device("cuda:0")
     n, K, C = 4096, 500, 50
-    U0, f, t = synthetic.adjoint_c5(n)
+    U0, f, t = synthetic.adjoint_gaussians(n)
     h2 = synthetic.spacing2(n)
     U0d = torch.from_numpy(U0.astype(np.float32)).to(dev)
     fd = torch.from_numpy(f.astype(np.float32)).to(dev)
@@ -190,7 +190,7 @@ def bench_poisson3d(plain_glups):
     import synthetic
     dev = torch.device("cuda:0")
     n, K, R = 512, 200, 20
-    U0, f = synthetic.poisson3d_c3(n)
+    U0, f = synthetic.poisson3d_uniform(n)
     h2 = synthetic.spacing2(n)
     out = {"workload": "3D 7-point Poisson 512^3, 8x8x8 blocks of 64^3, 200 sweeps, residual "
                        "every 20"}

@@ -10,17 +10,21 @@ oracle then sees those rounded values widened back to FP64).
 
 Workload recipes (the paper measures on no public data set; all inputs are
 synthetic, shaped like the Jacobi3D proxy's domain of Section 4.3):
-  laplace2d_c1   256^2 interior, ring: top edge (y = 1) = 1.0, other edges and
-                 the corners 0.0; interior u_0 ~ U[0,1) from default_rng(1).
-  poisson2d_c2   8192^2 interior, f = sum of 16 Gaussians (default_rng(2)),
-                 zero ring, u_0 = 0.
-  poisson3d_c3   512^3 interior, f ~ U[-1,1) (default_rng(3)), zero ring, u_0 = 0.
-  batched_c4     64 grids, sides n_g ~ integers in [257, 4097] from
-                 default_rng(4); f_g Gaussian sums from default_rng(4000+g);
-                 zero ring, u_0 = 0.
-  adjoint_c5     4096^2, f and target Gaussian sums (default_rng(5), (6)); ring
-                 values ~ U[0,1) on non-corner ring nodes (default_rng(7)),
-                 corners 0; u_0 = 0; finite-difference picks from default_rng(8).
+  laplace2d_top_edge   256^2 interior, ring: top edge (y = 1) = 1.0, other
+                       edges and the corners 0.0; interior u_0 ~ U[0,1) from
+                       default_rng(1).
+  poisson2d_gaussians  8192^2 interior, f = sum of 16 Gaussians
+                       (default_rng(2)), zero ring, u_0 = 0.
+  poisson3d_uniform    512^3 interior, f ~ U[-1,1) (default_rng(3)), zero
+                       ring, u_0 = 0.
+  batched_sizes / batched_source
+                       64 grids, sides n_g ~ integers in [257, 4097] from
+                       default_rng(4); f_g Gaussian sums from
+                       default_rng(4000+g); zero ring, u_0 = 0.
+  adjoint_gaussians    4096^2, f and target Gaussian sums (default_rng(5),
+                       (6)); ring values ~ U[0,1) on non-corner ring nodes
+                       (default_rng(7)), corners 0; u_0 = 0;
+                       finite-difference picks from default_rng(8).
 """
 import numpy as np
 
@@ -78,20 +82,20 @@ def state_with_ring(interior, ring=None):
     return U
 
 
-def laplace2d_c1(n=256, seed=1):
-    """Config 1: ring top edge (row y index n+1) = 1.0, else 0; u_0 ~ U[0,1)."""
+def laplace2d_top_edge(n=256, seed=1):
+    """256^2 Laplace case: ring top edge (row y index n+1) = 1.0, else 0; u_0 ~ U[0,1)."""
     U = np.zeros((n + 2, n + 2), dtype=np.float64)
     U[n + 1, 1:n + 1] = 1.0
     U[1:n + 1, 1:n + 1] = uniform((n, n), seed)
     return U
 
 
-def poisson2d_c2(n=8192, seed=2):
+def poisson2d_gaussians(n=8192, seed=2):
     """Config 2: returns (U0 zero everywhere, f Gaussian sum)."""
     return np.zeros((n + 2, n + 2), dtype=np.float64), gaussian_sum(n, 2, seed)
 
 
-def poisson3d_c3(n=512, seed=3):
+def poisson3d_uniform(n=512, seed=3):
     """Config 3: returns (U0 zero, f ~ U[-1,1))."""
     return (np.zeros((n + 2,) * 3, dtype=np.float64), uniform((n, n, n), seed, -1.0, 1.0))
 
@@ -126,7 +130,7 @@ def ring_mask(n, ndim):
     return on == 1
 
 
-def adjoint_c5(n=4096):
+def adjoint_gaussians(n=4096):
     """Config 5: returns (U0 with ring ~ U[0,1) and zero interior, f, target)."""
     U0 = ring_values(n, 2, 7)
     f = gaussian_sum(n, 2, 5)

@@ -70,7 +70,7 @@ def test_poisson3d_512_full(device, dtype):
     import torch
     import paper_2303_02543_amd as jb
     n, K, R = 512, 200, 20
-    U0, f = synthetic.poisson3d_c3(n)
+    U0, f = synthetic.poisson3d_uniform(n)
     U0 = U0.astype(dtype)
     fd = f.astype(dtype)
     h2 = synthetic.spacing2(n)
@@ -133,7 +133,7 @@ def adjoint_4096(device):
     import paper_2303_02543_amd as jb
     from paper_2303_02543_amd.autograd import JacobiK
     n, K, C = 4096, 500, 50
-    U0, f, t = synthetic.adjoint_c5(n)
+    U0, f, t = synthetic.adjoint_gaussians(n)
     U0, f, t = U0.astype(np.float32), f.astype(np.float32), t.astype(np.float32)
     h2 = synthetic.spacing2(n)
     s = jb.Solver((n, n), (8, 8), torch.float32, device=device)

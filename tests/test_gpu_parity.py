@@ -30,17 +30,17 @@ def assert_bits(got, want, what):
         raise AssertionError("%s: not bit-exact; first mismatch %s" % (what, mm))
 
 
-# ------------------------------------------------------------------ config 1
+# ------------------------------------------- 256^2 Laplace FP64, 2x2 blocks
 @pytest.mark.parametrize("depth,flags", [(1, 0), (2, 0), (3, 0), (4, 0), (1, 1), (1, 9)])
-def test_config1_bit_exact(device, depth, flags):
+def test_laplace256_fp64_bit_exact(device, depth, flags):
     """2D Laplace 256^2 FP64, 2x2 blocks of 128^2, 100 sweeps, residual every 10:
     bit-exact with the monolithic oracle; residuals within 1e-12."""
-    say("config1 depth=%d flags=%d" % (depth, flags))
-    U0 = synthetic.laplace2d_c1()
+    say("laplace 256^2 depth=%d flags=%d" % (depth, flags))
+    U0 = synthetic.laplace2d_top_edge()
     got, res = run_device(U0, None, 0.0, 100, (2, 2), np.float64, device, depth=depth,
                           flags=flags, check_every=10)
     want = oracle.sweep(U0, None, 100)
-    assert_bits(got, want, "config1")
+    assert_bits(got, want, "laplace 256^2")
     ores, _ = oracle_residuals(U0, None, 100, 10)
     np.testing.assert_allclose(res, ores, rtol=1e-12, atol=0)
 

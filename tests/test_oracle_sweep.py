@@ -227,8 +227,8 @@ def test_blocked_equals_monolithic_3d(dtype, n, nb):
     assert bits_equal(mono, blk)
 
 
-def test_config1_blocked_equals_monolithic():
-    U = synthetic.laplace2d_c1()
+def test_laplace256_blocked_equals_monolithic():
+    U = synthetic.laplace2d_top_edge()
     mono = oracle.sweep(U, None, 100)
     blk = oracle.blocked_sweep(U, None, 100, [oracle.balanced_starts(256, 2)] * 2)
     assert bits_equal(mono, blk)
