@@ -192,7 +192,8 @@ int check_handle(jacobi_t h) {
 }
 
 // Tile height that makes one march launch fill the GPU in `rounds` whole
-// rounds of resident waves: strips x tiles ~= rounds x (waves per CU x CUs).
+// rounds of resident waves: the smallest height whose tiles (edge bands and
+// outer strips included) number at most rounds x (waves per CU x CUs).
 int balanced_rows(const jacobi_s *h, int depth, int mode, int rounds, int deep) {
     if (h->g.ndim != 2) return 64;
     int cus = 0, dev = 0;
@@ -202,15 +203,25 @@ int balanced_rows(const jacobi_s *h, int depth, int mode, int rounds, int deep) 
         return 64;
     const int wpc = h->dtype == JACOBI_F32 ? jac::march2d_waves_per_cu<float>(depth, mode, deep)
                                            : jac::march2d_waves_per_cu<double>(depth, mode, deep);
-    const int64_t strips = h->dtype == JACOBI_F32 ? jac::march2d_strips<float>(h->g, depth)
-                                                  : jac::march2d_strips<double>(h->g, depth);
-    if (wpc <= 0 || strips <= 0) return 64;
-    int64_t tiles = (int64_t)rounds * wpc * cus / strips;
-    if (tiles < 1) tiles = 1;
-    int64_t rows = (h->g.n[1] + tiles - 1) / tiles;
-    if (rows < kMinRows) rows = kMinRows;
-    if (rows > (1 << 20)) rows = 1 << 20;
-    return (int)rows;
+    if (wpc <= 0) return 64;
+    const int64_t slots = (int64_t)rounds * wpc * cus;
+    auto tiles = [&](int rows) {
+        return h->dtype == JACOBI_F32 ? jac::march2d_work_items<float>(h->g, depth, rows)
+                                      : jac::march2d_work_items<double>(h->g, depth, rows);
+    };
+    int lo = kMinRows, hi = h->g.n[1] > kMinRows ? h->g.n[1] : kMinRows;
+    if (hi > (1 << 20)) hi = 1 << 20;
+    const int64_t most = tiles(hi);
+    if (most < 0 || most > slots) return hi;  // more strips than one round holds
+    while (lo < hi) {
+        const int mid = lo + (hi - lo) / 2;
+        const int64_t n = tiles(mid);
+        if (n >= 0 && n <= slots)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
 }
 
 // Defaults before any tuning: the fastest schedule measured on MI355X for a

@@ -68,6 +68,61 @@ struct M2 {
     static constexpr int RA = T + 1 <= 2 ? 2 : T + 1 <= 3 ? 3 : T + 1 <= 4 ? 4 : T + 1 <= 6 ? 6 : 12;
 };
 
+// Tiling of a pass over an nx x ny grid.  Strips of OW output columns;
+// the inner strips 1 .. ns-2 are cut into a band of he rows at the top, one
+// at the bottom, and tiles of `rows` rows between them; the outer strips 0
+// and ns-1 into tiles of he rows throughout.  A tile that reaches the
+// Dirichlet ring (an outer strip, or a band) runs the edge body, which
+// issues about 1.6x the instructions per step of the interior body, and a
+// tile of h rows takes h + 2T steps; with (he + 2T) = (rows + 2T) * 5/8 the
+// edge tiles take about as long as the interior ones, so a pass, whose
+// tiles all run as one generation of waves, is not held up by its edges.
+struct M2Tiles {
+    int ns, he, sa, sb, na, nb;  // strips, band height, tiles per inner / outer strip, inner / outer strips
+    int64_t ninner, nwork;       // tiles of the inner strips, all tiles
+};
+__host__ __device__ inline M2Tiles m2_tiles(int nx, int ny, int ow, int rows, int T) {
+    M2Tiles t;
+    t.ns = (nx + ow - 1) / ow;
+    const int lo = rows < 8 ? rows : 8;
+    int he = (rows + 2 * T) * 5 / 8 - 2 * T;
+    he = he > lo ? he : lo;
+    t.he = he < ny ? he : ny;
+    const int mid = ny - 2 * t.he;
+    t.sa = ny <= t.he ? 1 : 2 + (mid > 0 ? (mid + rows - 1) / rows : 0);
+    t.sb = (ny + t.he - 1) / t.he;
+    t.na = t.ns > 2 ? t.ns - 2 : 0;
+    t.nb = t.ns < 2 ? t.ns : 2;
+    t.ninner = (int64_t)t.na * t.sa;
+    t.nwork = t.ninner + (int64_t)t.nb * t.sb;
+    return t;
+}
+// Strip and output rows [oy0, oy1) of tile w (0 <= w < nwork).  Adjacent
+// tiles of the inner strips are adjacent strips of one row segment.
+__host__ __device__ inline void m2_tile(const M2Tiles &t, int ny, int rows, int64_t w,
+                                        int &strip, int &oy0, int &oy1) {
+    if (w < t.ninner) {
+        strip = 1 + (int)(w % t.na);
+        const int seg = (int)(w / t.na);
+        if (seg == 0) {
+            oy0 = 0;
+            oy1 = t.he;
+        } else if (seg == t.sa - 1) {
+            oy0 = ny - t.he > t.he ? ny - t.he : t.he;
+            oy1 = ny;
+        } else {
+            oy0 = t.he + (seg - 1) * rows;
+            oy1 = oy0 + rows < ny - t.he ? oy0 + rows : ny - t.he;
+        }
+    } else {
+        const int64_t v = w - t.ninner;
+        strip = t.nb == 2 && (v & 1) ? t.ns - 1 : 0;
+        const int seg = (int)(t.nb == 2 ? v >> 1 : v);
+        oy0 = seg * t.he;
+        oy1 = oy0 + t.he < ny ? oy0 + t.he : ny;
+    }
+}
+
 // Row cursor: global row y, its block row / local row, and the element
 // offsets of that row's start in the state and source buffers (all uniform).
 struct Cur {
@@ -386,16 +441,15 @@ __device__ __forceinline__ void m2_run(const Geom &g, const R *__restrict__ uin,
     constexpr bool SRC = MODE == MODE_POISSON;
     constexpr int V = S::V;
     const int lane = threadIdx.x & 63;
-    // adjacent work items are adjacent strips of one row segment, so the
-    // waves of a workgroup walk neighbouring columns of the same rows
-    const int nstrips = (g.n[0] + S::OW - 1) / S::OW;
-    const int strip = wid % nstrips, seg = wid / nstrips;
     const int nx = g.n[0], ny = g.n[1];
+    const M2Tiles tl = m2_tiles(nx, ny, S::OW, rows, T);
+    int strip, oy0, oy1;
+    m2_tile(tl, ny, rows, wid, strip, oy0, oy1);
     const int a = strip * S::OW - S::A0;  // first column held by the strip
     MLane L;
     L.bs = SRC ? (void *)(bs_wave + lane) : nullptr;
-    L.oy0 = seg * rows;
-    L.oy1 = L.oy0 + rows < ny ? L.oy0 + rows : ny;
+    L.oy0 = oy0;
+    L.oy1 = oy1;
     L.r1 = L.oy1 - 1 + T;
     const int c = a + lane * V;
     L.c = c;
@@ -497,12 +551,9 @@ __global__ __launch_bounds__(256) void k_march2d_batch(const BatchGrid *__restri
 // sees the per-depth launchers as declarations and instantiates no kernel.
 
 template <typename R, int T>
-static int64_t m2_nwork(const Geom &g, int rows, int *nseg_out) {
+static int64_t m2_nwork(const Geom &g, int rows) {
     using S = M2<R, T, 1>;  // the tiling does not depend on the prefetch distance
-    const int64_t nstrips = (g.n[0] + S::OW - 1) / S::OW;
-    const int64_t nseg = (g.n[1] + rows - 1) / rows;
-    if (nseg_out) *nseg_out = (int)nseg;
-    return nstrips * nseg;
+    return m2_tiles(g.n[0], g.n[1], S::OW, rows, T).nwork;
 }
 
 // deep != 0: the kernels that load three rows ahead (otherwise one)
@@ -559,7 +610,7 @@ template <typename R, int T>
 hipError_t m2_launch_t(const Geom &g, const void *uin, void *uout, const void *b, double *res,
                        double *gacc, int rows, hipStream_t st, int64_t *nwork_out, int nt,
                        int deep) {
-    const int64_t nwork = m2_nwork<R, T>(g, rows, nullptr);
+    const int64_t nwork = m2_nwork<R, T>(g, rows);
     if (nwork_out) *nwork_out = nwork;
     if (nwork > 0x7fffffff - 3) return hipErrorInvalidValue;
     if (deep && !gacc)
@@ -675,13 +726,9 @@ int march2d_waves_per_cu(int depth, int mode, int deep) {
 
 template <typename R>
 int64_t march2d_work_items(const Geom &g, int depth, int rows) {
-    JAC_M2_SWITCH(depth, m2_nwork, R, (int64_t)-1, g, rows, nullptr)
+    JAC_M2_SWITCH(depth, m2_nwork, R, (int64_t)-1, g, rows)
 }
 
-template <typename R>
-int64_t march2d_strips(const Geom &g, int depth) {
-    return march2d_work_items<R>(g, depth, g.n[1]);  // one tile per strip
-}
 
 template <typename R>
 hipError_t launch_sweep2d_march(const Geom &g, const void *uin, void *uout, const void *b,
@@ -693,7 +740,7 @@ hipError_t launch_sweep2d_march(const Geom &g, const void *uin, void *uout, cons
 
 template <typename R>
 int64_t march2d_batch_work(const Geom &g, int depth, int rows) {
-    JAC_M2_SWITCH(depth, m2_nwork, R, (int64_t)-1, g, rows, nullptr)
+    JAC_M2_SWITCH(depth, m2_nwork, R, (int64_t)-1, g, rows)
 }
 
 template <typename R>
@@ -723,8 +770,6 @@ template int64_t march2d_work_items<float>(const Geom &, int, int);
 template int64_t march2d_work_items<double>(const Geom &, int, int);
 template int march2d_waves_per_cu<float>(int, int, int);
 template int march2d_waves_per_cu<double>(int, int, int);
-template int64_t march2d_strips<float>(const Geom &, int);
-template int64_t march2d_strips<double>(const Geom &, int);
 
 #endif  // JAC_MARCH2D_DEPTH
 

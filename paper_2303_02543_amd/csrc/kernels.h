@@ -52,9 +52,6 @@ int64_t march2d_work_items(const Geom &g, int depth, int rows);
 // unknown.
 template <typename R>
 int march2d_waves_per_cu(int depth, int mode, int deep = 0);
-// Strips (work items per tile row) of the depth-`depth` march kernel.
-template <typename R>
-int64_t march2d_strips(const Geom &g, int depth);
 // Depths compiled for the 2D march kernel, ascending; returns the count.
 int march2d_depths(int dtype, const int **list);
 
