@@ -73,8 +73,10 @@ struct M2 {
 // at the bottom, and tiles of `rows` rows between them; the outer strips 0
 // and ns-1 into tiles of he rows throughout.  A tile that reaches the
 // Dirichlet ring (an outer strip, or a band) runs the edge body, which
-// issues about 1.6x the instructions per step of the interior body, and a
-// tile of h rows takes h + 2T steps; with (he + 2T) = (rows + 2T) * 5/8 the
+// issues about 1.6x the instructions per step of the interior body (and
+// takes about 1.46x the time: the measured fastest band height on MI355X
+// lies between fractions 5/8 and 3/4 of the interior tile below), and a tile
+// of h rows takes h + 2T steps; with (he + 2T) = (rows + 2T) * 11/16 the
 // edge tiles take about as long as the interior ones, so a pass, whose
 // tiles all run as one generation of waves, is not held up by its edges.
 struct M2Tiles {
@@ -85,7 +87,7 @@ __host__ __device__ inline M2Tiles m2_tiles(int nx, int ny, int ow, int rows, in
     M2Tiles t;
     t.ns = (nx + ow - 1) / ow;
     const int lo = rows < 8 ? rows : 8;
-    int he = (rows + 2 * T) * 5 / 8 - 2 * T;
+    int he = (rows + 2 * T) * 11 / 16 - 2 * T;
     he = he > lo ? he : lo;
     t.he = he < ny ? he : ny;
     const int mid = ny - 2 * t.he;
