@@ -99,6 +99,43 @@ def test_2d_bit_exact_all_depths(device, dtype, case):
     assert_bits(got, want, "2d non-temporal stores %s" % (case,))
 
 
+# The 2D pass tiling: inner strips get an edge band of he rows at the top and
+# the bottom and tiles of `rows` rows between, outer strips tiles of he rows,
+# with he = max(min(rows, 8), (rows + 2T) * 11 // 16 - 2T), capped at ny.
+# FP32 strips hold 248 output columns at depth 4 and 232 at depth 13.
+BAND_CASES = [
+    # (nx, ny, bx, by, depth, rows): the tiling case it reaches
+    (700, 20, 3, 2, 4, 40),   # 3 strips; ny <= he = 25: one band per inner strip
+    (700, 40, 3, 4, 4, 40),   # he < ny <= 2 he: a top band and a bottom band only
+    (700, 131, 3, 4, 4, 40),  # bands of 25, middle tiles of 40, 40 and a 1-row tail
+    (100, 131, 2, 3, 4, 40),  # one strip: outer-strip tiles only
+    (300, 131, 2, 3, 4, 40),  # two strips: outer-strip tiles only
+    (700, 131, 3, 4, 13, 8),  # depth 13, he clamped to 8 rows
+    (1200, 300, 4, 3, 13, 60),  # six strips, he = 33, ragged middle tile
+]
+
+
+@pytest.mark.parametrize("case", BAND_CASES)
+def test_2d_edge_band_tiling(device, case):
+    """Every tiling case of the 2D pass (band-only strips, bands with and
+    without middle tiles, a ragged middle tile, one and two strips): FP32
+    states bit-exact with the oracle's FP32 twin, with the residual folded
+    into the passes, for Poisson and Laplace."""
+    nx, ny, bx, by, depth, rows = case
+    U0 = RNG.uniform(0, 1, (ny + 2, nx + 2))
+    f = RNG.standard_normal((ny, nx)) * 100
+    h2 = synthetic.spacing2(max(nx, ny))
+    K = 2 * depth + 3
+    for src in (f, None):
+        want, b = oracle_run(U0, src, h2, K, np.float32)
+        ores, _ = oracle_residuals(np.asarray(U0, dtype=np.float32), b, K, depth)
+        say("2d band tiling case=%s source=%s" % (case, src is not None))
+        got, res = run_device(U0, src, h2, K, (bx, by), np.float32, device, depth=depth,
+                              rows=rows, check_every=depth)
+        assert_bits(got, want, "2d band tiling %s" % (case,))
+        np.testing.assert_allclose(res, ores, rtol=1e-12, atol=0)
+
+
 @pytest.mark.parametrize("flags", [0, 4])
 @pytest.mark.parametrize("case", [(37, 29, 3, 4, 13), (513, 260, 3, 5, 25), (1, 1, 1, 1, 3)])
 def test_2d_residuals_and_states(device, case, flags):
