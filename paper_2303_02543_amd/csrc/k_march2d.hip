@@ -166,6 +166,7 @@ struct MRegs {
     R l0[S::LR][S::V];       // level-0 rows, slot = row mod LR (r-2 .. r+P)
     R e0[S::LR];             // level-0 cell just outside the strip (lanes 0, 63)
     R bq[S::BQ][S::V];       // source rows in flight, slot = row mod BQ
+    R bn[2][S::V];           // source rows read ahead from LDS, slot = level mod 2
     R lv[S::NL][3][S::V];    // levels 1..T-1, slot = step mod 3
     double ga[S::RA][S::V];  // adjoint: FP64 accumulator rows r-T+1 .. r+1
     double acc;              // residual partial sum (level 1)
@@ -247,6 +248,18 @@ __device__ __forceinline__ void m2_accumulate(const Geom &g, double *__restrict_
     }
 }
 
+// Read the source row of level S (row r - S) from the wave's LDS ring into
+// bn[S & 1].  Issued one level before its use, so the LDS latency overlaps
+// the arithmetic of the level in between.
+template <typename R, int T, int P, int S>
+__device__ __forceinline__ void m2_read_src(const MLane &L, MRegs<R, T, P> &m, const int sr) {
+    using M = M2<R, T, P>;
+    const int slot = sr - S < 0 ? sr - S + M::RB : sr - S;
+    const Chunk<R, M::V> c = static_cast<const Chunk<R, M::V> *>(L.bs)[slot * 64];
+#pragma unroll
+    for (int v = 0; v < M::V; ++v) m.bn[S & 1][v] = c.v[v];
+}
+
 // Level S of step J (row r = base + J): computes row r - S from the three
 // newest rows of level S - 1 (level 0 = the loaded rows).  All ring slots are
 // compile-time constants so the rings live in registers.
@@ -275,12 +288,11 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
                 dn[v] = m.lv[S - 2][J % 3][v];
             }
         }
-        R bv[V];  // source row r - S from the wave's LDS ring
+        R bv[V];  // source row r - S, read from the wave's LDS ring one level ahead
         if constexpr (SRC) {
-            const int slot = sr - S < 0 ? sr - S + M::RB : sr - S;
-            const Chunk<R, V> c = static_cast<const Chunk<R, V> *>(L.bs)[slot * 64];
 #pragma unroll
-            for (int v = 0; v < V; ++v) bv[v] = c.v[v];
+            for (int v = 0; v < V; ++v) bv[v] = m.bn[S & 1][v];
+            if constexpr (S < T) m2_read_src<R, T, P, S + 1>(L, m, sr);
         }
         R out[V];
         if (!EDGE || (y >= 0 && y < ny)) {
@@ -383,6 +395,7 @@ __device__ __forceinline__ void m2_steps(const Geom &g, const R *__restrict__ ui
             for (int v = 0; v < V; ++v) v0[v] = m.l0[J % M::LR][v];
             m2_accumulate<R, T, P, MODE, EDGE, J % M::RA, T == 1>(g, gacc, L, m, r, v0);
         }
+        if constexpr (MODE == MODE_POISSON) m2_read_src<R, T, P, 1>(L, m, sr);
         m2_level<R, T, P, MODE, EDGE, RES, J, 1>(g, uout, gacc, L, m, r, sc, sr);
         sc.advance(g);
         sr = sr + 1 == M::RB ? 0 : sr + 1;
