@@ -158,9 +158,11 @@ int jacobi_solve(jacobi_t h, int64_t n_iter, int64_t check_every, double *res_de
 /* Choose the sweep schedule.  t_depth: sweeps per pass (temporal blocking,
  * 1..jacobi_max_depth(); 0 = library default; a depth without a compiled
  * kernel is run as passes of the nearest smaller compiled depths).
- * rows (0 = default): rows per tile of the 2D pass (>= 8), z planes per
- * work item of the 3D pass (>= 8), or, with JACOBI_FLAG_EXPLICIT_HALO on a
- * 2D grid, rows per work item of the block-local sweep (>= 1).
+ * rows (0 = default): rows per interior tile of the 2D pass (>= 8; tiles
+ * that reach the grid's boundary ring get fewer rows, derived from this
+ * height, because they run a slower edge step), z planes per work item of
+ * the 3D pass (>= 8), or, with JACOBI_FLAG_EXPLICIT_HALO on a 2D grid, rows
+ * per work item of the block-local sweep (>= 1).
  * flags: jacobi_flags.  JACOBI_E_INVAL for values out of range.
  * Bit-neutral: every choice gives the same results. */
 int jacobi_set_tuning(jacobi_t h, int t_depth, int rows, int flags);
