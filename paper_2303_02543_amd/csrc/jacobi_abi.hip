@@ -380,8 +380,13 @@ int do_sweep_overlap(jacobi_t h, int64_t n, double *res_first) {
 
 // n sweeps; if res_first is not NULL, the FP64 residual of the state the call
 // starts from is written there (folded into the first pass when possible).
+// The fused passes read a block-edge neighbour from the block that owns it
+// and never the stored halos, so they refresh the halos (for the API's
+// other paths) only once, after their last pass, and only when
+// sync_halos is set; the explicit-halo sweep keeps them valid after every
+// sweep, as it must.
 template <typename R>
-int do_sweep(jacobi_t h, int64_t n, double *res_first) {
+int do_sweep(jacobi_t h, int64_t n, double *res_first, bool sync_halos = true) {
     const void *b = h->has_source ? h->b : nullptr;
     const bool explicit_halo = (h->flags & JACOBI_FLAG_EXPLICIT_HALO) != 0 ||
                                (h->g.ndim == 2 && !march_fits(h->g, h->dtype));
@@ -405,7 +410,9 @@ int do_sweep(jacobi_t h, int64_t n, double *res_first) {
                         "residual launch");
             h->cur ^= 1;
         }
-        HIP_TRY(jac::launch_halo_exchange<R>(h->g, h->u[h->cur], h->stream), "halo exchange launch");
+        if (sync_halos)
+            HIP_TRY(jac::launch_halo_exchange<R>(h->g, h->u[h->cur], h->stream),
+                    "halo exchange launch");
         return JACOBI_OK;
     }
     if ((h->flags & JACOBI_FLAG_OVERLAP) && explicit_halo) return do_sweep_overlap<R>(h, n, res_first);
@@ -460,7 +467,9 @@ int do_sweep(jacobi_t h, int64_t n, double *res_first) {
         h->cur ^= 1;
         left -= t;
     }
-    HIP_TRY(jac::launch_halo_exchange<R>(h->g, h->u[h->cur], h->stream), "halo exchange launch");
+    if (sync_halos)
+        HIP_TRY(jac::launch_halo_exchange<R>(h->g, h->u[h->cur], h->stream),
+                "halo exchange launch");
     return JACOBI_OK;
 }
 
@@ -679,12 +688,15 @@ int jacobi_solve(jacobi_t h, int64_t n_iter, int64_t check_every, double *res_de
     if (!res_dev) return fail(JACOBI_E_INVAL, "res_dev must not be NULL");
     if (!h->has_state) return fail(JACOBI_E_STATE, "no state set (call jacobi_set_state first)");
     // the residual of the state at the start of each interval rides on the
-    // interval's first pass; the final state's residual needs its own pass
+    // interval's first pass; the final state's residual needs its own pass.
+    // Halos are refreshed after the last interval only (the fused passes
+    // and their residuals do not read them).
     int64_t k = 0, i = 0;
     while (k < n_iter) {
         const int64_t step = n_iter - k < check_every ? n_iter - k : check_every;
-        rc = h->dtype == JACOBI_F32 ? do_sweep<float>(h, step, res_dev + i)
-                                    : do_sweep<double>(h, step, res_dev + i);
+        const bool last = k + step >= n_iter;
+        rc = h->dtype == JACOBI_F32 ? do_sweep<float>(h, step, res_dev + i, last)
+                                    : do_sweep<double>(h, step, res_dev + i, last);
         if (rc) return rc;
         k += step;
         ++i;
