@@ -87,6 +87,9 @@ enum jacobi_flags {
 /* ---------------------------------------------------------------- set-up */
 
 /* Device bytes the handle needs for this problem.
+ * Implements: the decomposition of the domain into cuboid blocks (Section
+ * 4.3, and more blocks than processing elements in Section 4.4); the sizes
+ * and the 32-byte x granularity are this library's choice.
  *   ndim    2 or 3
  *   grid    interior nodes per axis, x first (ndim values, each >= 1)
  *   blocks  blocks per axis, x first (ndim values, 1 <= blocks <= grid);
@@ -98,64 +101,91 @@ enum jacobi_flags {
 int jacobi_workspace_bytes(int ndim, const int64_t *grid, const int64_t *blocks, int dtype,
                            size_t *bytes);
 
-/* Create a handle over a caller-owned device workspace (256-byte aligned,
+/* Implements: Section 4.3's cuboid decomposition, as block storage in one
+ * device workspace.
+ * Create a handle over a caller-owned device workspace (256-byte aligned,
  * >= jacobi_workspace_bytes).  stream: hipStream_t to enqueue on, or NULL for
  * the null stream.  The handle starts without a state (JACOBI_E_STATE from
  * sweep/residual until jacobi_set_state) and without a source (Laplace). */
 int jacobi_create(int ndim, const int64_t *grid, const int64_t *blocks, int dtype,
                   void *workspace, size_t workspace_bytes, void *stream, jacobi_t *out);
 
-/* Wait for the handle's stream, then free the host object.  NULL is a no-op. */
+/* Library plumbing (no passage).  Wait for the handle's stream, then free
+ * the host object.  NULL is a no-op.  The workspace stays the caller's. */
 int jacobi_destroy(jacobi_t h);
 
-/* Rebind the handle to another stream (hipStream_t; NULL = null stream). */
+/* Library plumbing (no passage).  Rebind the handle to another stream
+ * (hipStream_t; NULL = null stream); later calls enqueue there. */
 int jacobi_set_stream(jacobi_t h, void *stream);
 
-/* Block geometry: per axis x first, blocks and block extent (3 values each,
- * unused axes 1). */
+/* Implements: Section 4.3's cuboid blocks, reported.  Block geometry per
+ * axis x first: blocks and block extent (3 host int64 values each, unused
+ * axes 1).  JACOBI_E_INVAL if either pointer is NULL. */
 int jacobi_get_layout(jacobi_t h, int64_t *blocks3, int64_t *extent3);
 
 /* ------------------------------------------------------- data in and out */
 
-/* Scatter a full state (ring + interior, layout above) into the blocks of
- * both state buffers and fill every block's halo (Section 4.3: the domain is
- * decomposed into cuboids).  u: device, handle dtype. */
+/* Implements: Section 4.3, the domain decomposed into cuboids, each with its
+ * face halos.  Scatter a full state (ring + interior, layout above) into the
+ * blocks of both state buffers and fill every block's halo.  u: device,
+ * handle dtype, read when the stream reaches the call.  JACOBI_E_INVAL if u
+ * is NULL. */
 int jacobi_set_state(jacobi_t h, const void *u);
 
-/* Gather the current state (ring + interior) into u (device, handle dtype). */
+/* Implements: the inverse of the Section 4.3 decomposition.  Gather the
+ * current state (ring + interior) into u (device, handle dtype, caller-owned).
+ * JACOBI_E_STATE before jacobi_set_state. */
 int jacobi_get_state(jacobi_t h, void *u);
 
-/* Set the scaled source b = fl_T(h2 * f) blockwise, with the product formed in
+/* Not in the paper (its proxy states no equation): the right-hand side of
+ * the Poisson reading -Laplace(u) = f.
+ * Set the scaled source b = fl_T(h2 * f) blockwise, with the product formed in
  * FP64 and rounded once to the handle dtype T.  f: device interior array of
  * the handle dtype, or NULL for the Laplace equation (b = 0).  h2 > 0, finite. */
 int jacobi_set_source(jacobi_t h, const void *f, double h2);
 
 /* ------------------------------------------------------------- hot path */
 
-/* Refresh every internal face halo of the current state buffer from the face
+/* Implements: Section 4.3, packing each block's face data, moving it to the
+ * face neighbour and unpacking it into that block's halo (in HBM here).
+ * Refresh every internal face halo of the current state buffer from the face
  * neighbour's edge cells (pack, copy, unpack in HBM; one launch for all faces
  * of all blocks).  Domain-edge halos keep the boundary values.  Idempotent. */
 int jacobi_halo_exchange(jacobi_t h);
 
-/* Run n_iter >= 0 synchronous sweeps (0 is a no-op).  The sweeps are grouped
+/* Implements: Section 4.3, the Jacobi update run for a fixed number of
+ * iterations once the halos are in (the exchange is fused into the pass
+ * kernels' loads, or run explicitly with JACOBI_FLAG_EXPLICIT_HALO).
+ * Run n_iter >= 0 synchronous sweeps (0 is a no-op).  The sweeps are grouped
  * into passes of up to the tuned temporal depth; every pass reads the current
  * buffer and writes the other.  Halos are valid when the last pass ends. */
 int jacobi_sweep(jacobi_t h, int64_t n_iter);
 
-/* FP64 residual of the current state, written to the device double *res_dev
+/* Not in the paper (its proxy runs a fixed iteration count): the FP64 L2
+ * residual of the Poisson reading, the step whose cancellation needs FP64.
+ * FP64 residual of the current state, written to the device double *res_dev
  * (stream-ordered, no synchronisation, deterministic summation order). */
 int jacobi_residual_async(jacobi_t h, double *res_dev);
 
-/* Same, copied to the host double *res_host; synchronises the stream. */
+/* Not in the paper (as jacobi_residual_async).  Same value, copied to the
+ * host double *res_host; synchronises the stream. */
 int jacobi_residual(jacobi_t h, double *res_host);
 
-/* Sweep n_iter times, taking the residual of the states after 0, R, 2R, ...
+/* Implements: Section 4.3's iteration loop, with the residual check (not in
+ * the paper) every R sweeps.
+ * Sweep n_iter times, taking the residual of the states after 0, R, 2R, ...
  * sweeps and after the last sweep: res_dev receives
  * ceil(n_iter / R) + 1 device doubles (R = check_every >= 1).  Stream-ordered,
  * no host synchronisation. */
 int jacobi_solve(jacobi_t h, int64_t n_iter, int64_t check_every, double *res_dev);
 
-/* Choose the sweep schedule.  t_depth: sweeps per pass (temporal blocking,
+/* Not in the paper (performance only; Section 4.4's over-decomposition is
+ * the JACOBI_FLAG_OVERLAP schedule).  The paper's interface has no knobs;
+ * the three here are the ones the kernels have: depth (sweeps per pass),
+ * rows (the tile height of the 2D pass / z segment of the 3D pass, which
+ * fixes the tile width too) and flags (schedule forms).  Tile width is not a
+ * separate knob: a lane handles 16 bytes of a row and a wave 64 lanes.
+ * Choose the sweep schedule.  t_depth: sweeps per pass (temporal blocking,
  * 1..jacobi_max_depth(); 0 = library default; a depth without a compiled
  * kernel is run as passes of the nearest smaller compiled depths).
  * rows (0 = default): rows per interior tile of the 2D pass (>= 8; tiles
@@ -168,11 +198,14 @@ int jacobi_solve(jacobi_t h, int64_t n_iter, int64_t check_every, double *res_de
 int jacobi_set_tuning(jacobi_t h, int t_depth, int rows, int flags);
 int jacobi_get_tuning(jacobi_t h, int *t_depth, int *rows, int *flags);
 
-/* Largest temporal depth this build supports for the handle's ndim/dtype. */
+/* Not in the paper.  Largest temporal depth this build supports for the
+ * ndim/dtype (JACOBI_E_INVAL for unknown ones). */
 int jacobi_max_depth(int ndim, int dtype);
 
 /* --------------------------------------------------------------- batched */
 /*
+ * Not in the paper: the batched form of the method (the paper runs one
+ * domain).  Each grid is decomposed and swept as in Section 4.3.
  * Many independent 2D Poisson grids of uneven sizes solved together: every
  * pass is one launch over the tiles of all grids that are still active, the
  * FP64 residual of each grid is folded into the first pass of each check
@@ -194,43 +227,52 @@ enum jacobi_batch_status {
     JACOBI_DIVERGED = 3
 };
 
-/* Workspace for `count` grids; grids: count pairs (n_x, n_y) of interior
+/* Batched form (not in the paper); Section 4.3's decomposition per grid.
+ * Workspace for `count` grids; grids: count pairs (n_x, n_y) of interior
  * sizes (host array); block: target block side (>= 8; blocks per axis =
  * ceil(n / block), reduced if the last block would be empty).  dtype as for
  * jacobi_create. */
 int jacobi_batch_workspace_bytes(int count, const int64_t *grids, int64_t block, int dtype,
                                  size_t *bytes);
 
-/* Create a batch over a caller-owned device workspace (256-byte aligned).
+/* Batched form (not in the paper); Section 4.3's block storage per grid.
+ * Create a batch over a caller-owned device workspace (256-byte aligned).
  * stream: hipStream_t; hipGraph capture needs a non-NULL stream (with NULL
  * the intervals are launched one kernel at a time). */
 int jacobi_batch_create(int count, const int64_t *grids, int64_t block, int dtype,
                         void *workspace, size_t workspace_bytes, void *stream,
                         jacobi_batch_t *out);
 
-/* Wait for the stream, release graphs and host memory.  NULL is a no-op. */
+/* Library plumbing.  Wait for the stream, release graphs and host memory.
+ * NULL is a no-op. */
 int jacobi_batch_destroy(jacobi_batch_t b);
 
-/* Set grid i: u full state (ring + interior) and f interior source, both
+/* Implements: Section 4.3's scatter into cuboids, per grid.  JACOBI_E_INVAL
+ * for a bad index, NULL pointers or a bad h2.
+ * Set grid i: u full state (ring + interior) and f interior source, both
  * device arrays of the batch dtype in the single-grid layout; b = fl(h2 f).
  * Every grid must be set before a solve. */
 int jacobi_batch_set_grid(jacobi_batch_t b, int i, const void *u, const void *f, double h2);
 
-/* Gather grid i's final state (the state its stop test was taken on) into u. */
+/* Implements: the inverse of Section 4.3's decomposition, per grid.
+ * JACOBI_E_STATE for a grid never set.  Gather grid i's final state (the state its stop test was taken on) into u. */
 int jacobi_batch_get_grid(jacobi_batch_t b, int i, void *u);
 
-/* Schedule: temporal depth (0 = default), tile rows (0 = default, else >= 8),
+/* Not in the paper (performance only).  Schedule: temporal depth (0 = default), tile rows (0 = default, else >= 8),
  * use_graph (replay captured check intervals). */
 int jacobi_batch_set_tuning(jacobi_batch_t b, int t_depth, int rows, int use_graph);
 int jacobi_batch_get_tuning(jacobi_batch_t b, int *t_depth, int *rows, int *use_graph);
 
-/* Time candidate depths and tile heights on one check interval of
+/* Not in the paper (the batched form's autotuner).  Time candidate depths and
+ * tile heights on one check interval of
  * check_every sweeps and keep the fastest (all are bit-identical).  Uses the
  * grids' buffers as scratch: every grid must be set again afterwards.
  * Synchronises the stream.  Outputs may be NULL. */
 int jacobi_batch_autotune(jacobi_batch_t b, int64_t check_every, int *t_depth, int *rows);
 
-/* Solve every grid with the stop rule above.  Host outputs (count entries
+/* Implements: Section 4.3's iteration loop over every grid at once, with the
+ * stop rule above (not in the paper).  JACOBI_E_STATE if a grid is not set.
+ * Solve every grid with the stop rule above.  Host outputs (count entries
  * each, may be NULL): sweeps of the final state, its relative residual, and
  * the jacobi_batch_status.  Synchronises the stream. */
 int jacobi_batch_solve(jacobi_batch_t b, double rel_tol, int64_t max_sweeps, int64_t check_every,
@@ -238,8 +280,8 @@ int jacobi_batch_solve(jacobi_batch_t b, double rel_tol, int64_t max_sweeps, int
 
 /* --------------------------------------------------------------- adjoint */
 /*
- * Reverse-mode derivative through K 2D sweeps (not in the paper; the
- * differentiable form of the sweep).  One sweep is the affine map
+ * Not in the paper: the differentiable form of the Section 4.3 sweep.
+ * Reverse-mode derivative through K 2D sweeps.  One sweep is the affine map
  * u_k = w (S u_{k-1} + B g + b), w = 1/4, with S the neighbour sum over the
  * interior (zero ring, symmetric) and B moving each ring value into its one
  * adjacent interior node.  Given lam_K = dL/du_K, the adjoint runs
@@ -251,9 +293,38 @@ int jacobi_batch_solve(jacobi_batch_t b, double rel_tol, int64_t max_sweeps, int
  * 2D only (JACOBI_E_UNSUPPORTED for 3D handles).
  */
 
-/* Start an adjoint run: the handle's state becomes lam (device full state
- * array of the handle dtype whose interior holds dL/du_K; its ring is read as
- * zero), and grad_b (device FP64 interior array, n_y x n_x, x fastest,
+/* Forward K >= 0 sweeps from the current state (as jacobi_sweep), saving a
+ * checkpoint every C >= 1 sweeps: ckpt (device, caller-owned, or NULL for
+ * none) receives ceil(K / C) full states of the handle dtype back to back,
+ * the states after 0, C, 2C, ... sweeps (k < K).  Afterwards the handle holds
+ * u_K.  The checkpoints are restart points of the forward run; the adjoint
+ * below does not read them (the sweep is affine, so the lam recurrence needs
+ * no forward state).  JACOBI_E_STATE before jacobi_set_state. */
+int jacobi_forward_ckpt(jacobi_t h, int64_t K, int64_t C, void *ckpt);
+
+/* Gradients of a loss L(u_K) after K sweeps with respect to the source and
+ * the whole initial state, in one call; the adjoint sweeps run in segments of
+ * C >= 1 (any C gives the same bits).
+ *   dL_duK  device full state of the handle dtype: dL/du_K at every node,
+ *           ring included (the sweeps copy the ring, so the ring of u_K is
+ *           g and its gradient passes to g unchanged)
+ *   h2      h^2 > 0 of the forward run (b = h2 f)
+ *   dL_df   device FP64 interior array (n_y x n_x, x fastest): dL/df.  Also
+ *           the accumulator during the run.
+ *   dL_dU0  device FP64 full array ((n_y+2) x (n_x+2)), distinct from
+ *           dL_df: interior = dL/du_0 = lam_0; non-corner ring node q =
+ *           dL_duK[q] + Gb[p(q)]; corner = dL_duK[corner].
+ * Runs on the handle's stream, no synchronisation.  Uses the handle's state
+ * buffers: afterwards the state is lam_0 with a zero ring.  2D only
+ * (JACOBI_E_UNSUPPORTED otherwise); JACOBI_E_INVAL for NULL pointers, K < 0,
+ * C < 1, a bad h2 or dL_df == dL_dU0. */
+int jacobi_adjoint(jacobi_t h, int64_t K, int64_t C, const void *dL_duK, double h2,
+                   double *dL_df, double *dL_dU0);
+
+/* The same run in three calls, for callers that drive the segments
+ * themselves.  Start an adjoint run: the handle's state becomes lam (device
+ * full state array of the handle dtype whose interior holds dL/du_K; its
+ * ring is read as zero), and grad_b (device FP64 interior array, n_y x n_x, x fastest,
  * caller-owned) is zeroed and becomes the accumulator.  grad_b must stay
  * valid until jacobi_adjoint_end. */
 int jacobi_adjoint_begin(jacobi_t h, const void *lam, double *grad_b);
@@ -266,18 +337,21 @@ int jacobi_adjoint_sweep(jacobi_t h, int64_t n_iter);
 
 /* Finish: grad_f (device FP64 interior array, may be NULL, may alias
  * grad_b) = h2 * grad_b; grad_ring (device FP64 full (n_y+2) x (n_x+2) array,
- * may be NULL) = dL/dg on non-corner ring nodes, 0 on corners and interior. */
+ * may be NULL) = the part of dL/dg that flows through the sweeps, Gb[p(q)],
+ * on non-corner ring nodes, 0 on corners and interior.  A loss that also
+ * reads the ring of u_K adds its gradient there itself (jacobi_adjoint
+ * does). */
 int jacobi_adjoint_end(jacobi_t h, double h2, double *grad_f, double *grad_ring);
 
 /* ------------------------------------------------------------ profiling */
 
-/* Start (enable != 0) or stop recording a pair of HIP events on the handle's
+/* Not in the paper (measurement).  Start (enable != 0) or stop recording a pair of HIP events on the handle's
  * stream around every sweep-kernel launch (the pass kernels of jacobi_sweep
  * and jacobi_solve).  Enabling discards earlier records.  Recording adds no
  * device work besides the event markers. */
 int jacobi_profile(jacobi_t h, int enable);
 
-/* Summarise the records: launches of passes of `depth` sweeps (0 = all
+/* Not in the paper (measurement).  Summarise the records: launches of passes of `depth` sweeps (0 = all
  * launches).  Outputs: summed kernel time in milliseconds, number of
  * launches, cell updates performed (interior cells times sweeps) and
  * algorithmic HBM bytes (per pass: one read of the state and the source and
@@ -286,7 +360,7 @@ int jacobi_profile(jacobi_t h, int enable);
 int jacobi_profile_read(jacobi_t h, int depth, double *ms, int64_t *launches,
                         double *cell_updates, double *alg_bytes);
 
-/* Pick the sweep schedule by timing.  Runs jacobi_sweep(n_sweeps) on the
+/* Not in the paper (performance only).  Pick the sweep schedule by timing.  Runs jacobi_sweep(n_sweeps) on the
  * handle's own buffers for each candidate temporal depth and tile height
  * (plus the explicit-halo schedule) and keeps the fastest; every candidate
  * computes identical results, so the choice never changes any output.
@@ -300,6 +374,8 @@ int jacobi_autotune(jacobi_t h, int64_t n_sweeps, int with_source, int *t_depth,
                     int *flags);
 
 /* --------------------------------------------------------------- errors */
+/* Library plumbing.  Static text of a status; the last error's message on
+ * the calling thread (valid until that thread's next failing call). */
 const char *jacobi_strerror(int status);
 const char *jacobi_last_error(void);
 

@@ -267,6 +267,24 @@ def adjoint2d(lamK, K):
     return Gb, Gring, lam0
 
 
+def adjoint2d_full(dLduK, K):
+    """Adjoint through K 2D sweeps for a loss that reads all of u_K.
+
+    dLduK: full array (ny+2, nx+2) of dL/du_K, ring included.  A sweep copies
+    the ring, so the ring of u_K is the boundary data g itself and dL/du_K on
+    the ring passes to g unchanged; the interior part runs through the FP64
+    recurrence of adjoint2d.  Returns (Gb over the interior, dL/dU0 over all
+    nodes: interior lam_0, non-corner ring Gring + dL/du_K, corners dL/du_K)."""
+    dLduK = np.asarray(dLduK, dtype=np.float64)
+    Gb, Gring, lam0 = adjoint2d(np.ascontiguousarray(interior(dLduK)), K)
+    dU0 = Gring.copy()
+    ring = np.ones(dLduK.shape, dtype=bool)
+    interior(ring)[...] = False
+    dU0[ring] = Gring[ring] + dLduK[ring]
+    interior(dU0)[...] = lam0
+    return Gb, dU0
+
+
 def gradients2d(U0, f, h2, target, K):
     """FP64 gradients of L = 1/2 ||u_K - t||^2 with respect to the source f and
     the full initial state U0 (ring = boundary values g, interior = u_0).
@@ -285,10 +303,16 @@ def gradients2d(U0, f, h2, target, K):
 
 def fd_difference_loss(uplus, uminus, target):
     """L(u+) - L(u-) summed cell by cell as sum (u+ - u-) * ((u+ + u-)/2 - t),
-    which avoids cancelling two large sums against each other."""
-    a = interior(uplus).astype(np.float64)
-    c = interior(uminus).astype(np.float64)
+    which avoids cancelling two large sums against each other.  The loss is
+    over the interior when target has the interior shape, over every node
+    (ring included) when it has the full shape."""
     t = np.asarray(target, dtype=np.float64)
+    if t.shape == uplus.shape:
+        a = np.asarray(uplus, dtype=np.float64)
+        c = np.asarray(uminus, dtype=np.float64)
+    else:
+        a = interior(uplus).astype(np.float64)
+        c = interior(uminus).astype(np.float64)
     return float(np.sum((a - c) * (0.5 * (a + c) - t)))
 
 

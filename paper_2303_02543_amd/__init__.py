@@ -72,6 +72,8 @@ _SIGNATURES = {
     "jacobi_batch_get_tuning": [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)],
     "jacobi_batch_autotune": [_P, _I64, ctypes.POINTER(_I), ctypes.POINTER(_I)],
     "jacobi_batch_solve": [_P, _D, _I64, _I64, _PI64, ctypes.POINTER(_D), ctypes.POINTER(_I)],
+    "jacobi_forward_ckpt": [_P, _I64, _I64, _P],
+    "jacobi_adjoint": [_P, _I64, _I64, _P, _D, _P, _P],
     "jacobi_adjoint_begin": [_P, _P, _P],
     "jacobi_adjoint_sweep": [_P, _I64],
     "jacobi_adjoint_end": [_P, _D, _P, _P],
@@ -279,6 +281,14 @@ def jacobi_batch_solve(b, count, rel_tol, max_sweeps, check_every):
     return list(sw), list(rl), list(st)
 
 
+def jacobi_forward_ckpt(h, K, C, ckpt_ptr):
+    _check(lib().jacobi_forward_ckpt(h, int(K), int(C), ckpt_ptr))
+
+
+def jacobi_adjoint(h, K, C, dL_duK_ptr, h2, dL_df_ptr, dL_dU0_ptr):
+    _check(lib().jacobi_adjoint(h, int(K), int(C), dL_duK_ptr, float(h2), dL_df_ptr, dL_dU0_ptr))
+
+
 def jacobi_adjoint_begin(h, lam_ptr, grad_b_ptr):
     _check(lib().jacobi_adjoint_begin(h, lam_ptr, grad_b_ptr))
 
@@ -425,11 +435,37 @@ class Solver:
     def get_tuning(self):
         return jacobi_get_tuning(self.h)
 
-    def adjoint(self, lam_K, n_iter, h2, chunk=None, checkpoints=None):
-        """Reverse sweeps: from dL/du_K (full state tensor, ring ignored) return
-        (dL/df FP64 interior, dL/dU0 as a full FP64 array: ring = dL/dg,
-        interior = dL/du_0).  chunk: sweeps per adjoint segment (checkpoint
-        interval); checkpoints: optional list that receives lam at every
+    def forward_ckpt(self, n_iter, chunk, keep=True):
+        """n_iter sweeps from the current state; with keep, returns the
+        checkpoints (states after 0, C, 2C, ... sweeps, C = chunk) as one
+        device tensor of shape (ceil(n_iter / C),) + state_shape, else None."""
+        import torch
+        n_iter, chunk = int(n_iter), int(chunk)
+        ck = None
+        if keep and n_iter > 0:
+            ck = torch.empty((-(-n_iter // chunk),) + self.state_shape, dtype=self.torch_dtype,
+                             device=self.device)
+        jacobi_forward_ckpt(self.h, n_iter, chunk, _ptr(ck))
+        return ck
+
+    def adjoint(self, dL_duK, n_iter, h2, chunk=None):
+        """Reverse sweeps in one library call (jacobi_adjoint): from dL/du_K
+        (full state tensor, ring included) return (dL/df FP64 interior,
+        dL/dU0 FP64 full array: ring = dL/dg, interior = dL/du_0).  chunk:
+        sweeps per adjoint segment (the gradients do not depend on it)."""
+        import torch
+        self._check_tensor(dL_duK, self.state_shape, "dL_duK")
+        gf = torch.empty(self.interior_shape, dtype=torch.float64, device=self.device)
+        gU0 = torch.empty(self.state_shape, dtype=torch.float64, device=self.device)
+        chunk = int(n_iter) if not chunk else int(chunk)
+        jacobi_adjoint(self.h, n_iter, max(chunk, 1), _ptr(dL_duK), h2, _ptr(gf), _ptr(gU0))
+        return gf, gU0
+
+    def adjoint_segments(self, lam_K, n_iter, h2, chunk=None, lam_checkpoints=None):
+        """The same reverse sweeps through jacobi_adjoint_begin / _sweep / _end.
+        Returns (dL/df, the ring part of dL/dg that flows through the sweeps
+        as a full FP64 array, lam_0 as a state tensor); lam_K's ring is read
+        as zero.  lam_checkpoints: optional list that receives lam at every
         segment boundary (device tensors)."""
         import torch
         self._check_tensor(lam_K, self.state_shape, "lam_K")
@@ -442,13 +478,10 @@ class Solver:
             step = min(chunk, left)
             jacobi_adjoint_sweep(self.h, step)
             left -= step
-            if checkpoints is not None:
-                checkpoints.append(self.get_state())
+            if lam_checkpoints is not None:
+                lam_checkpoints.append(self.get_state())
         jacobi_adjoint_end(self.h, h2, _ptr(gb), _ptr(ring))
-        lam0 = self.get_state()
-        grad_u0 = ring
-        grad_u0[(slice(1, -1),) * self.ndim] = lam0[(slice(1, -1),) * self.ndim].to(torch.float64)
-        return gb, grad_u0
+        return gb, ring, self.get_state()
 
     def profile(self, enable=True):
         jacobi_profile(self.h, enable)

@@ -36,9 +36,14 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
-def _compile(unit, verbose):
+def _compile(unit, verbose, incremental=False):
     src, name, defines = unit
     obj = os.path.join(BUILD_DIR, name + ".o")
+    if incremental and os.path.exists(obj):
+        deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in HEADERS]
+        deps.append(os.path.join(ROOT, "include", "jacobi.h"))
+        if all(os.path.getmtime(d) <= os.path.getmtime(obj) for d in deps):
+            return obj
     cmd = [HIPCC] + FLAGS + defines + ["-I", os.path.join(ROOT, "include"), "-c",
                                        os.path.join(CSRC, src), "-o", obj]
     if verbose:
@@ -49,14 +54,16 @@ def _compile(unit, verbose):
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
-    """Compile every HIP source for gfx950 and link libjacobi.so.  Always rebuilds."""
+def build(verbose: bool = False, jobs: int = 8, incremental: bool = False) -> str:
+    """Compile every HIP source for gfx950 and link libjacobi.so.  Rebuilds
+    every object unless incremental (then only objects older than their
+    source or a header)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
         # the largest units first, so they do not end up last in the queue
         units = sorted(UNITS, key=lambda u: -int(u[1].rsplit("_d", 1)[-1])
                        if u[1].startswith("k_march2d_d") else 0)
-        objs = list(ex.map(lambda u: _compile(u, verbose), units))
+        objs = list(ex.map(lambda u: _compile(u, verbose, incremental), units))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
@@ -76,5 +83,5 @@ def is_stale() -> bool:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

@@ -752,6 +752,65 @@ int jacobi_adjoint_end(jacobi_t h, double h2, double *grad_f, double *grad_ring)
     return JACOBI_OK;
 }
 
+int jacobi_forward_ckpt(jacobi_t h, int64_t K, int64_t C, void *ckpt) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (K < 0) return fail(JACOBI_E_INVAL, "K must be >= 0 (got %lld)", (long long)K);
+    if (C < 1) return fail(JACOBI_E_INVAL, "C must be >= 1 (got %lld)", (long long)C);
+    if (!h->has_state) return fail(JACOBI_E_STATE, "no state set (call jacobi_set_state first)");
+    const size_t es = h->dtype == JACOBI_F32 ? 4 : 8;
+    const size_t state_bytes =
+        (size_t)(h->g.n[0] + 2) * (h->g.n[1] + 2) * (h->g.ndim == 3 ? h->g.n[2] + 2 : 1) * es;
+    int64_t k = 0, j = 0;
+    while (k < K) {
+        const int64_t step = K - k < C ? K - k : C;
+        if (ckpt) {
+            void *dst = (char *)ckpt + (size_t)j * state_bytes;
+            if (h->dtype == JACOBI_F32)
+                HIP_TRY(jac::launch_gather<float>(h->g, h->u[h->cur], dst, h->stream), "gather launch");
+            else
+                HIP_TRY(jac::launch_gather<double>(h->g, h->u[h->cur], dst, h->stream), "gather launch");
+        }
+        // the gather reads block interiors and the domain-edge halos only, so
+        // the internal halos are refreshed once, after the last segment
+        const bool last = k + step >= K;
+        rc = h->dtype == JACOBI_F32 ? do_sweep<float>(h, step, nullptr, last)
+                                    : do_sweep<double>(h, step, nullptr, last);
+        if (rc) return rc;
+        k += step;
+        ++j;
+    }
+    return JACOBI_OK;
+}
+
+int jacobi_adjoint(jacobi_t h, int64_t K, int64_t C, const void *dL_duK, double h2, double *dL_df,
+                   double *dL_dU0) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (K < 0) return fail(JACOBI_E_INVAL, "K must be >= 0 (got %lld)", (long long)K);
+    if (C < 1) return fail(JACOBI_E_INVAL, "C must be >= 1 (got %lld)", (long long)C);
+    if (!dL_duK || !dL_df || !dL_dU0)
+        return fail(JACOBI_E_INVAL, "dL_duK, dL_df and dL_dU0 must not be NULL");
+    if (!(h2 > 0.0) || !std::isfinite(h2))
+        return fail(JACOBI_E_INVAL, "h2 must be positive and finite (got %g)", h2);
+    if ((void *)dL_df == (void *)dL_dU0) return fail(JACOBI_E_INVAL, "dL_df and dL_dU0 must differ");
+    rc = jacobi_adjoint_begin(h, dL_duK, dL_df);
+    if (rc) return rc;
+    for (int64_t k = 0; k < K && !rc; k += C) rc = jacobi_adjoint_sweep(h, K - k < C ? K - k : C);
+    if (rc) {
+        h->gacc = nullptr;
+        return rc;
+    }
+    // dL/dU0 reads the accumulator before it is scaled in place into dL/df
+    if (h->dtype == JACOBI_F32)
+        HIP_TRY(jac::launch_adjoint_full<float>(h->g, dL_df, dL_duK, h->u[h->cur], dL_dU0, h->stream),
+                "adjoint finish launch");
+    else
+        HIP_TRY(jac::launch_adjoint_full<double>(h->g, dL_df, dL_duK, h->u[h->cur], dL_dU0, h->stream),
+                "adjoint finish launch");
+    return jacobi_adjoint_end(h, h2, dL_df, nullptr);
+}
+
 int jacobi_set_tuning(jacobi_t h, int t_depth, int rows, int flags) {
     int rc = check_handle(h);
     if (rc) return rc;

@@ -202,6 +202,48 @@ __global__ __launch_bounds__(256) void k_adjoint_ring(int nx, int ny, const doub
     }
 }
 
+// Full dL/dU0 of a 2D adjoint run whose loss reads all of u_K (ring
+// included).  A sweep copies the ring, so the ring of u_K is g itself and
+// each ring node gets dL/du_K there plus, for non-corner nodes, what flowed
+// through the sweeps (gb at its interior neighbour); corners get only
+// dL/du_K.  Interior nodes get lam_0, read from the blocked state s.
+template <typename R>
+__global__ __launch_bounds__(256) void k_adjoint_full(Geom g, const double *__restrict__ gb,
+                                                      const R *__restrict__ lamK,
+                                                      const R *__restrict__ s,
+                                                      double *__restrict__ out, int64_t total) {
+    const int nx = g.n[0], ny = g.n[1];
+    const int64_t nx2 = nx + 2;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx2) - 1;
+        const int y = (int)(i / nx2) - 1;
+        const bool inx = x >= 0 && x < nx, iny = y >= 0 && y < ny;
+        double v;
+        if (inx && iny) {
+            v = (double)s[state_offset(g, x, y, 0)];
+        } else {
+            v = (double)lamK[i];
+            if (inx) v = v + gb[(int64_t)(y < 0 ? 0 : ny - 1) * nx + x];
+            if (iny) v = v + gb[(int64_t)y * nx + (x < 0 ? 0 : nx - 1)];
+        }
+        out[i] = v;
+    }
+}
+
+template <typename R>
+hipError_t launch_adjoint_full(const Geom &g, const double *gb, const void *lamK, const void *s,
+                               double *out, hipStream_t st) {
+    const int64_t total = (int64_t)(g.n[0] + 2) * (g.n[1] + 2);
+    hipLaunchKernelGGL(k_adjoint_full<R>, dim3(grid_for(total)), dim3(256), 0, st, g, gb,
+                       (const R *)lamK, (const R *)s, out, total);
+    return hipGetLastError();
+}
+template hipError_t launch_adjoint_full<float>(const Geom &, const double *, const void *,
+                                               const void *, double *, hipStream_t);
+template hipError_t launch_adjoint_full<double>(const Geom &, const double *, const void *,
+                                                const void *, double *, hipStream_t);
+
 __global__ __launch_bounds__(256) void k_scale_f64(const double *gb, double h2, double *out,
                                                    int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;

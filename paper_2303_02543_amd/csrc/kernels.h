@@ -14,6 +14,12 @@ hipError_t launch_scatter(const Geom &g, const void *u, void *s0, void *s1, bool
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t st);
 hipError_t launch_adjoint_finish(const Geom &g, const double *gb, double h2, double *grad_f,
                                  double *grad_ring, hipStream_t st);
+// Full FP64 dL/dU0 ((n_y+2) x (n_x+2)) of a 2D adjoint run: interior =
+// lam_0 from the blocked state s; ring = lamK's ring (the loss's gradient on
+// the ring of u_K) plus, off the corners, gb at the adjacent interior node.
+template <typename R>
+hipError_t launch_adjoint_full(const Geom &g, const double *gb, const void *lamK, const void *s,
+                               double *out, hipStream_t st);
 template <typename R>
 hipError_t launch_gather(const Geom &g, const void *s, void *u, hipStream_t st);
 template <typename R>

@@ -122,6 +122,21 @@ def test_batch_arguments_rejected():
     assert L.jacobi_adjoint_begin(None, None, None) == jb.JACOBI_E_INVAL
     assert L.jacobi_adjoint_sweep(None, 1) == jb.JACOBI_E_INVAL
     assert L.jacobi_adjoint_end(None, 1.0, None, None) == jb.JACOBI_E_INVAL
+    assert L.jacobi_forward_ckpt(None, 10, 5, None) == jb.JACOBI_E_INVAL
+    assert L.jacobi_adjoint(None, 10, 5, None, 1.0, None, None) == jb.JACOBI_E_INVAL
+
+
+def test_adjoint_entry_points_declared_with_their_arguments():
+    # the one-call checkpointed forward / adjoint pair is part of the ABI
+    text = open(os.path.join(ROOT, "include", "jacobi.h")).read()
+    assert re.search(r"int jacobi_forward_ckpt\(jacobi_t h, int64_t K, int64_t C, void \*ckpt\);",
+                     text)
+    assert re.search(r"int jacobi_adjoint\(jacobi_t h, int64_t K, int64_t C, const void \*dL_duK, "
+                     r"double h2,\s+double \*dL_df, double \*dL_dU0\);", text)
+    L = jb.lib()
+    assert L.jacobi_forward_ckpt.argtypes == [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                              ctypes.c_void_p]
+    assert len(L.jacobi_adjoint.argtypes) == 7
 
 
 def test_strerror_and_depths():

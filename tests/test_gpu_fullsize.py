@@ -1,5 +1,6 @@
 """Parity at the workloads' full sizes, in the launch configurations the
-benchmark uses (autotuned schedule, same call sequence).  The oracle computes
+benchmark uses (the library default 2D schedule and the autotuned one, the
+autotuned batch and 3D schedules, same call sequence).  The oracle computes
 each full run once on the host's cores (FP32 runs against the oracle's FP32
 twin bit for bit, and against the FP64 oracle within 1e-5 norm-relative)."""
 import math
@@ -32,41 +33,60 @@ def residual_history(U0, b, K, R):
     return U, np.array(res)
 
 
-def test_poisson2d_8192_full(device):
-    """2D Poisson 8192^2 FP32, 16x16 blocks, 1000 sweeps, residual every 50:
-    the whole final state bit-exact with the FP32 oracle twin, every residual
-    within 1e-12, and the state within 1e-5 of the FP64 oracle."""
-    import torch
-    import paper_2303_02543_amd as jb
+@pytest.fixture(scope="module")
+def poisson2d_8192_oracle():
+    """The oracle's FP32 twin of the 8192^2 workload (final state and every
+    residual) and the FP64 oracle's final state, computed once."""
     n, K, R = 8192, 1000, 50
     f32 = synthetic.gaussian_sum(n, 2, 2).astype(np.float32)
     U0 = np.zeros((n + 2, n + 2), dtype=np.float32)
     h2 = synthetic.spacing2(n)
+    b32 = oracle.scale_source(f32, h2, np.float32)
+    want, ores = residual_history(U0, b32, K, R)
+    b64 = oracle.scale_source(f32.astype(np.float64), h2, np.float64)
+    ref = oracle.sweep(U0.astype(np.float64), b64, K)
+    return dict(n=n, K=K, R=R, f32=f32, U0=U0, h2=h2, want=want, ores=ores, ref=ref)
+
+
+@pytest.mark.parametrize("schedule", ["library_default", "autotuned"])
+def test_poisson2d_8192_full(device, poisson2d_8192_oracle, schedule):
+    """2D Poisson 8192^2 FP32, 16x16 blocks, 1000 sweeps, residual every 50,
+    in the benchmark's schedule (the library default: depth 13, balanced
+    151-row tiles) and in the autotuner's pick: the whole final state
+    bit-exact with the FP32 oracle twin, every residual within 1e-12, and
+    the state within 1e-5 of the FP64 oracle."""
+    import torch
+    import paper_2303_02543_amd as jb
+    o = poisson2d_8192_oracle
+    n, K, R = o["n"], o["K"], o["R"]
     s = jb.Solver((n, n), (16, 16), torch.float32, device=device)
     try:
-        d, r, fl = s.autotune(R, with_source=True)
-        say("8192^2 schedule depth=%d rows=%d flags=%d" % (d, r, fl))
-        s.set_source(torch.from_numpy(f32).to(device), h2)
-        s.set_state(torch.from_numpy(U0).to(device))
+        if schedule == "autotuned":
+            s.autotune(R, with_source=True)
+        else:
+            s.set_tuning(0, 0, 0)
+        s.set_source(torch.from_numpy(o["f32"]).to(device), o["h2"])
+        d, r, fl = s.get_tuning()
+        say("8192^2 %s schedule depth=%d rows=%d flags=%d" % (schedule, d, r, fl))
+        s.set_state(torch.from_numpy(o["U0"]).to(device))
         res = s.solve(K, R).cpu().numpy()
         got = s.get_state().cpu().numpy()
     finally:
         s.close()
-    b32 = oracle.scale_source(f32, h2, np.float32)
-    want, ores = residual_history(U0, b32, K, R)
-    if not bits_equal(got, want):
-        raise AssertionError("8192^2 not bit-exact: %s" % (first_mismatch(got, want),))
-    np.testing.assert_allclose(res, ores, rtol=1e-12, atol=0)
-    b64 = oracle.scale_source(f32.astype(np.float64), h2, np.float64)
-    ref = oracle.sweep(U0.astype(np.float64), b64, K)
-    err = norm_rel_err(got, ref)
+    if not bits_equal(got, o["want"]):
+        raise AssertionError("8192^2 not bit-exact: %s" % (first_mismatch(got, o["want"]),))
+    np.testing.assert_allclose(res, o["ores"], rtol=1e-12, atol=0)
+    err = norm_rel_err(got, o["ref"])
     say("8192^2 FP32 vs FP64 rel err %.3e" % err)
     assert err <= 1e-5
 
 
+@pytest.mark.parametrize("schedule", ["library_default", "autotuned"])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-def test_poisson3d_512_full(device, dtype):
-    """3D Poisson 512^3, 8x8x8 blocks of 64^3, 200 sweeps, residual every 20."""
+def test_poisson3d_512_full(device, dtype, schedule):
+    """3D Poisson 512^3, 8x8x8 blocks of 64^3, 200 sweeps, residual every 20,
+    in the library's default schedule and in the autotuner's pick (the
+    benchmark's)."""
     import torch
     import paper_2303_02543_amd as jb
     n, K, R = 512, 200, 20
@@ -77,6 +97,9 @@ def test_poisson3d_512_full(device, dtype):
     tdt = torch.float32 if dtype == np.float32 else torch.float64
     s = jb.Solver((n, n, n), (8, 8, 8), tdt, device=device)
     try:
+        if schedule == "autotuned":
+            s.autotune(R, with_source=True)
+        say("512^3 %s schedule %s" % (schedule, s.get_tuning()))
         s.set_source(torch.from_numpy(fd).to(device), h2)
         s.set_state(torch.from_numpy(U0).to(device))
         res = s.solve(K, R).cpu().numpy()
@@ -123,6 +146,41 @@ def test_batched_64_grids_sampled(device):
         assert sw[g] == out["sweeps"] and jb.STATUS_NAMES[st[g]] == out["status"]
         assert math.isclose(rl[g], out["rel"], rel_tol=1e-12)
         assert bits_equal(finals[g], out["u"]), "batched grid %d" % g
+
+
+def test_batched_64_grids_all_500_sweeps(device):
+    """All 64 grids of the batch, in the benchmark's configuration (autotuned
+    schedule, graph-replayed intervals), after 500 sweeps with the residual
+    every 50: every grid's state bit-exact with the oracle's FP32 twin, and
+    its sweeps, status and relative residual equal to the oracle's stop-rule
+    solve."""
+    import torch
+    import paper_2303_02543_amd as jb
+    sizes = [int(n) for n in synthetic.batched_sizes()]
+    srcs = [synthetic.batched_source(n, g).astype(np.float32) for g, n in enumerate(sizes)]
+    B = jb.Batch([(n, n) for n in sizes], torch.float32, block=512, device=device)
+    try:
+        d, r = B.autotune(50)
+        B.set_tuning(d, r, True)
+        say("batch schedule depth=%d rows=%d" % (d, r))
+        for g, n in enumerate(sizes):
+            B.set_grid(g, torch.zeros((n + 2, n + 2), dtype=torch.float32, device=device),
+                       torch.from_numpy(srcs[g]).to(device), synthetic.spacing2(n))
+        sw, rl, st = B.solve(1e-6, 500, 50)
+        finals = [B.get_grid(g).cpu().numpy() for g in range(len(sizes))]
+    finally:
+        B.close()
+    bad = []
+    for g, n in enumerate(sizes):
+        b32 = oracle.scale_source(srcs[g], synthetic.spacing2(n), np.float32)
+        out = oracle.solve(np.zeros((n + 2, n + 2), np.float32), b32, 500, 50, 1e-6)
+        ok = (sw[g] == out["sweeps"] and jb.STATUS_NAMES[st[g]] == out["status"]
+              and math.isclose(rl[g], out["rel"], rel_tol=1e-12)
+              and bits_equal(finals[g], out["u"]))
+        if not ok:
+            bad.append((g, n))
+    say("batch 500 sweeps: %d of %d grids differ %s" % (len(bad), len(sizes), bad[:5]))
+    assert not bad
 
 
 @pytest.fixture(scope="module")

@@ -106,3 +106,29 @@ def test_central_finite_differences():
     for idx in g_idx:
         fd = oracle.fd_grad_state(U0, f, h2, t, K, idx, 1e-3)
         assert math.isclose(fd, dLdU0[idx], rel_tol=1e-6, abs_tol=1e-14)
+
+
+def test_full_state_loss_brute_force_differences():
+    # A loss over every node of u_K, ring included: L = 1/2 sum (u_K - T)^2.
+    # The ring of u_K is g itself (sweeps copy it), so dL/dg gains dL/du_K on
+    # the ring, corners included.  Checked against central differences of
+    # every entry of f and U0 on a tiny grid (L is quadratic: differences are
+    # exact up to rounding).
+    nx, ny, K = 6, 5, 4
+    h2 = synthetic.spacing2(max(nx, ny))
+    U0 = RNG.uniform(-1, 1, (ny + 2, nx + 2))
+    f = RNG.standard_normal((ny, nx))
+    T = RNG.standard_normal((ny + 2, nx + 2))
+    b = oracle.scale_source(f, h2)
+    uK = oracle.sweep(U0, b, K)
+    Gb, dU0 = oracle.adjoint2d_full(uK - T, K)
+    eps = 1e-3
+    for idx in np.ndindex(U0.shape):
+        fd = oracle.fd_grad_state(U0, f, h2, T, K, idx, eps)
+        assert math.isclose(fd, dU0[idx], rel_tol=1e-9, abs_tol=1e-12), idx
+    for idx in np.ndindex(f.shape):
+        fd = oracle.fd_grad_source(U0, f, h2, T, K, idx, eps)
+        assert math.isclose(fd, h2 * Gb[idx], rel_tol=1e-9, abs_tol=1e-15), idx
+    # corners only see the identity: dL/dU0 there is (u_K - T) at the corner
+    for c in [(0, 0), (0, -1), (-1, 0), (-1, -1)]:
+        assert dU0[c] == (uK - T)[c]

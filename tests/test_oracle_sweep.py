@@ -38,6 +38,26 @@ def test_constant_field_is_fixed_point_3d(dtype, c):
     assert bits_equal(oracle.sweep(U, None, 5), U)
 
 
+@pytest.mark.parametrize("dtype,c,fixed", [
+    (np.float64, 0.1, True), (np.float64, 0.3, False), (np.float32, 0.1, False)])
+def test_constant_field_3d_pins_multiply_by_rounded_sixth(dtype, c, fixed):
+    # The 7-point weight is applied as a multiply by fl(1/6), not a divide by
+    # 6 (the two round differently).  With the sum 6c formed by exact
+    # doublings and one rounded add, fl(6c) * fl(1/6) returns c for FP64 0.1
+    # but not for FP64 0.3 or FP32 0.1, while fl(6c) / 6 does the opposite in
+    # all three cases; so an oracle that divides fails every one of these.
+    c = dtype(c)
+    U = np.full((6, 7, 8), c, dtype=dtype)
+    V = oracle.sweep(U, None, 1)
+    inner = V[1:-1, 1:-1, 1:-1]
+    if fixed:
+        assert bits_equal(V, U)
+    else:
+        assert np.all(inner != c)
+        # still within an ulp of c: the multiply rounds twice
+        assert np.all(np.abs(inner.astype(np.float64) - float(c)) <= float(np.spacing(c)))
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_integer_linear_field_is_fixed_point(dtype):
     # discrete harmonic: neighbour sums are exact integers
