@@ -179,6 +179,33 @@ int jacobi_residual(jacobi_t h, double *res_host);
  * no host synchronisation. */
 int jacobi_solve(jacobi_t h, int64_t n_iter, int64_t check_every, double *res_dev);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * solve as jacobi_create over a workspace, then jacobi_set_source(f, h2),
+ * jacobi_set_state(u0), jacobi_solve(n_iter, check_every, res_dev) and
+ * jacobi_get_state(u_out), with the library's default schedule, but without
+ * a handle or a workspace: the library's own device scratch array (a fixed
+ * JACOBI_NOALLOC_MAX_BYTES bytes per GPU, reserved when the library first
+ * runs on that GPU and held until the process ends) stands in for the
+ * workspace.  Allocates nothing (no hipMalloc, hipFree or allocating library
+ * call); the first call on a device looks up that device's copy of the array.
+ *   ndim, grid, blocks, dtype  as for jacobi_workspace_bytes; a problem whose
+ *           workspace would exceed JACOBI_NOALLOC_MAX_BYTES is refused with
+ *           JACOBI_E_NOMEM (about 2048^2 FP32 in 4x4 blocks fits)
+ *   u0      device full state (ring + interior), handle-dtype layout above
+ *   f, h2   device interior source and h^2 (f NULL: Laplace, h2 ignored)
+ *   u_out   device full state receiving u after n_iter sweeps (may be u0)
+ *   res_dev ceil(n_iter / check_every) + 1 device doubles, as jacobi_solve
+ *   stream  hipStream_t or NULL; asynchronous, stream-ordered.
+ * Results are bit-identical to the handle path with the same blocks.  Every
+ * call on a GPU uses that GPU's one scratch array: calls that overlap on one
+ * GPU (two streams or two threads) race and give wrong results; the array
+ * keeps the last call's contents, which no later call reads before writing. */
+#define JACOBI_NOALLOC_MAX_BYTES (64u << 20)
+int jacobi_solve_noalloc(int ndim, const int64_t *grid, const int64_t *blocks, int dtype,
+                         const void *u0, const void *f, double h2, int64_t n_iter,
+                         int64_t check_every, void *u_out, double *res_dev, void *stream);
+
 /* Not in the paper (performance only; Section 4.4's over-decomposition is
  * the JACOBI_FLAG_OVERLAP schedule).  The paper's interface has no knobs;
  * the three here are the ones the kernels have: depth (sweeps per pass),

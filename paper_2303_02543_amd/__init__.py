@@ -60,6 +60,7 @@ _SIGNATURES = {
     "jacobi_residual_async": [_P, _P],
     "jacobi_residual": [_P, ctypes.POINTER(_D)],
     "jacobi_solve": [_P, _I64, _I64, _P],
+    "jacobi_solve_noalloc": [_I, _PI64, _PI64, _I, _P, _P, _D, _I64, _I64, _P, _P, _P],
     "jacobi_set_tuning": [_P, _I, _I, _I],
     "jacobi_get_tuning": [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)],
     "jacobi_max_depth": [_I, _I],
@@ -208,6 +209,16 @@ def jacobi_residual(h):
 
 def jacobi_solve(h, n_iter, check_every, res_ptr):
     _check(lib().jacobi_solve(h, int(n_iter), int(check_every), res_ptr))
+
+
+def jacobi_solve_noalloc(ndim, grid, blocks, dtype, u0_ptr, f_ptr, h2, n_iter, check_every,
+                         u_out_ptr, res_ptr, stream_ptr):
+    _check(lib().jacobi_solve_noalloc(int(ndim), _arr64(grid), _arr64(blocks), int(dtype),
+                                      u0_ptr, f_ptr, float(h2), int(n_iter), int(check_every),
+                                      u_out_ptr, res_ptr, stream_ptr))
+
+
+JACOBI_NOALLOC_MAX_BYTES = 64 << 20
 
 
 def jacobi_set_tuning(h, t_depth=0, rows=0, flags=0):

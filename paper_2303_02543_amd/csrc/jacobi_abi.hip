@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -150,6 +151,13 @@ int plan(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, Geom *
 }
 
 }  // namespace
+
+// Device scratch of jacobi_solve_noalloc: a file-scope array of fixed size,
+// one copy on every GPU the library runs on, held until the process ends.
+// In host code `scratch` names a host-side stand-in, never the device
+// memory: its device address is looked up once per device with
+// hipGetSymbolAddress and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[JACOBI_NOALLOC_MAX_BYTES];
 
 // Pieces of an overlapped explicit-halo sweep (slabs of block layers).
 constexpr int kPieces = 4;
@@ -500,6 +508,53 @@ int do_adjoint(jacobi_t h, int64_t n) {
     return JACOBI_OK;
 }
 
+// A fresh handle's fields over workspace ws (no state, no source, default
+// schedule, no profiling).
+void init_handle(jacobi_s *h, const Geom &g, const Layout &l, int dtype, void *ws, void *stream) {
+    h->g = g;
+    h->lay = l;
+    h->dtype = dtype;
+    h->ws = (char *)ws;
+    h->u[0] = h->ws + l.off_u0;
+    h->u[1] = h->ws + l.off_u1;
+    h->b = h->ws + l.off_b;
+    h->partials = (double *)(h->ws + l.off_part);
+    h->scratch = (double *)(h->ws + l.off_scratch);
+    h->cur = 0;
+    h->has_state = false;
+    h->has_source = false;
+    h->stream = (hipStream_t)stream;
+    h->depth = 0;
+    h->rows = 0;
+    h->flags = 0;
+    h->profiling = false;
+    h->adj_depth = 0;
+    h->adj_rows = 0;
+    h->gacc = nullptr;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`.
+int scratch_address(void **out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "get device");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(JACOBI_E_UNSUPPORTED, "device index %d beyond the %d the library tracks", dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch symbol address");
+        if (!p) return fail(JACOBI_E_HIP, "scratch symbol address is NULL");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return JACOBI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -535,26 +590,7 @@ int jacobi_create(int ndim, const int64_t *grid, const int64_t *blocks, int dtyp
         return fail(JACOBI_E_INVAL, "workspace is not device memory");
     jacobi_s *h = new (std::nothrow) jacobi_s();
     if (!h) return fail(JACOBI_E_NOMEM, "host allocation failed");
-    h->g = g;
-    h->lay = l;
-    h->dtype = dtype;
-    h->ws = (char *)workspace;
-    h->u[0] = h->ws + l.off_u0;
-    h->u[1] = h->ws + l.off_u1;
-    h->b = h->ws + l.off_b;
-    h->partials = (double *)(h->ws + l.off_part);
-    h->scratch = (double *)(h->ws + l.off_scratch);
-    h->cur = 0;
-    h->has_state = false;
-    h->has_source = false;
-    h->stream = (hipStream_t)stream;
-    h->depth = 0;
-    h->rows = 0;
-    h->flags = 0;
-    h->profiling = false;
-    h->adj_depth = 0;
-    h->adj_rows = 0;
-    h->gacc = nullptr;
+    init_handle(h, g, l, dtype, workspace, stream);
     *out = h;
     return JACOBI_OK;
 }
@@ -702,6 +738,37 @@ int jacobi_solve(jacobi_t h, int64_t n_iter, int64_t check_every, double *res_de
         ++i;
     }
     return jacobi_residual_async(h, res_dev + i);
+}
+
+int jacobi_solve_noalloc(int ndim, const int64_t *grid, const int64_t *blocks, int dtype,
+                         const void *u0, const void *f, double h2, int64_t n_iter,
+                         int64_t check_every, void *u_out, double *res_dev, void *stream) {
+    // every argument check before any HIP call
+    Geom g;
+    Layout l;
+    int rc = plan(ndim, grid, blocks, dtype, &g, &l);
+    if (rc != JACOBI_OK) return rc;
+    if (!u0 || !u_out || !res_dev) return fail(JACOBI_E_INVAL, "u0, u_out and res_dev must not be NULL");
+    if (n_iter < 0) return fail(JACOBI_E_INVAL, "n_iter must be >= 0");
+    if (check_every < 1) return fail(JACOBI_E_INVAL, "check_every must be >= 1");
+    if (f && (!(h2 > 0.0) || !std::isfinite(h2)))
+        return fail(JACOBI_E_INVAL, "h2 must be positive and finite (got %g)", h2);
+    if (l.bytes > (size_t)JACOBI_NOALLOC_MAX_BYTES)
+        return fail(JACOBI_E_NOMEM,
+                    "problem needs %zu bytes of device scratch; jacobi_solve_noalloc holds %zu "
+                    "(use jacobi_create with a workspace)",
+                    l.bytes, (size_t)JACOBI_NOALLOC_MAX_BYTES);
+    void *ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc != JACOBI_OK) return rc;
+    // a handle on the stack over the scratch: host metadata only, nothing to
+    // free afterwards (no profiling events, no second stream)
+    jacobi_s h;
+    init_handle(&h, g, l, dtype, ws, stream);
+    if ((rc = jacobi_set_source(&h, f, h2)) != JACOBI_OK) return rc;
+    if ((rc = jacobi_set_state(&h, u0)) != JACOBI_OK) return rc;
+    if ((rc = jacobi_solve(&h, n_iter, check_every, res_dev)) != JACOBI_OK) return rc;
+    return jacobi_get_state(&h, u_out);
 }
 
 int jacobi_adjoint_begin(jacobi_t h, const void *lam, double *grad_b) {

@@ -156,3 +156,32 @@ def test_solver_refuses_without_gpu():
         pytest.skip("a GPU is visible")
     with pytest.raises(RuntimeError, match="no GPU"):
         jb.Solver((16, 16), (2, 2), torch.float32)
+
+
+def test_noalloc_arguments_rejected_before_any_hip_call():
+    L = jb.lib()
+    p = ctypes.c_void_p(256)  # never dereferenced: every case fails its checks first
+    g, b = jb._arr64([64, 64]), jb._arr64([2, 2])
+    f = L.jacobi_solve_noalloc
+    assert f(2, g, b, 0, None, p, 1e-4, 10, 5, p, p, None) == jb.JACOBI_E_INVAL
+    assert f(2, g, b, 0, p, p, 1e-4, 10, 5, None, p, None) == jb.JACOBI_E_INVAL
+    assert f(2, g, b, 0, p, p, 1e-4, 10, 5, p, None, None) == jb.JACOBI_E_INVAL
+    assert f(2, g, b, 0, p, p, 1e-4, -1, 5, p, p, None) == jb.JACOBI_E_INVAL
+    assert f(2, g, b, 0, p, p, 1e-4, 10, 0, p, p, None) == jb.JACOBI_E_INVAL
+    assert f(2, g, b, 0, p, p, -1.0, 10, 5, p, p, None) == jb.JACOBI_E_INVAL
+    assert f(2, g, b, 9, p, p, 1e-4, 10, 5, p, p, None) == jb.JACOBI_E_INVAL
+    assert f(2, g, jb._arr64([65, 1]), 0, p, p, 1e-4, 10, 5, p, p, None) == jb.JACOBI_E_INVAL
+    # a workspace beyond the scratch array is refused with a clear message
+    big = jb._arr64([4096, 4096])
+    need = jb.jacobi_workspace_bytes(2, [4096, 4096], [8, 8], jb.JACOBI_F32)
+    assert need > jb.JACOBI_NOALLOC_MAX_BYTES
+    assert f(2, big, jb._arr64([8, 8]), 0, p, p, 1e-4, 10, 5, p, p, None) == jb.JACOBI_E_NOMEM
+    msg = jb.jacobi_last_error()
+    assert "scratch" in msg and str(need) in msg
+    # the limit in the binding is the header's
+    text = open(os.path.join(ROOT, "include", "jacobi.h")).read()
+    m = re.search(r"#define JACOBI_NOALLOC_MAX_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == jb.JACOBI_NOALLOC_MAX_BYTES
+    # a problem that fits passes every check (2048^2 FP32 in 4x4 blocks)
+    assert jb.jacobi_workspace_bytes(2, [2048, 2048], [4, 4], jb.JACOBI_F32) <= \
+        jb.JACOBI_NOALLOC_MAX_BYTES
