@@ -7,16 +7,21 @@ Workload (one "step" = one whole solve, every step of the hot path):
   over-decomposed into 16 x 16 blocks of 512^2 with one-cell halos;
   1000 sweeps with the residual taken every 50 sweeps (and at 0).
   Per step: scale the source into the blocks, scatter the initial state into
-  the blocks, 1000 sweeps (halo reads fused into the pass kernel, an explicit
-  halo exchange after each 50-sweep interval), 21 FP64 residuals, gather the
-  final state.  Inputs are resident in HBM before timing starts.
+  the blocks, 1000 sweeps (the pass kernels read a block-edge neighbour
+  straight from the block that owns it; the stored one-cell halos are
+  refreshed once, after the last pass), 21 FP64 residuals, gather the final
+  state.  Inputs are resident in HBM before timing starts.
 
 Output: one JSON line (see the fields below).  `value` is GLUP/s (10^9 interior
 cell updates per second) of the whole step.  `roofline` describes the dominant
 kernel (the sweep pass kernel), timed live with HIP events on its own stream;
-`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the workload.
+`cpu_baseline` times the FP64 CPU oracle on the workload (all host cores and
+one thread) and states every form's error against the FP64 oracle.
+`--only FORM` runs one form alone (for profiling its kernels) and prints its
+record.
 """
 import argparse
+import glob
 import hashlib
 import json
 import math
@@ -38,8 +43,8 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T ops/s
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 FLOPS_PER_UPDATE = 5  # (W+E), (S+N), their sum, +b: 4 adds; *w: 1 mul
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep2d_march_poisson8192.json")
-SWEEP_SOURCE = os.path.join(ROOT, "paper_2303_02543_amd", "csrc", "k_march2d.hip")
+REL_BOUND = 1e-5
+FORMS = ("batched", "adjoint", "poisson3d", "plain2d", "overdecomposition", "paper_domain_3d")
 
 
 def parse():
@@ -63,25 +68,41 @@ def parse():
                     help="run the whole workload on the oracle (and report the GPU result's "
                          "error against it) when it is estimated to take at most this long")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the batched and adjoint measurements")
+                    help="skip the batched, adjoint, 3D and plain-sweep measurements")
+    ap.add_argument("--only", choices=FORMS, default=None,
+                    help="run only this form (no headline solve, no oracle) and print its "
+                         "record; used to profile one form's kernels")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
-                    help="only run 5 plain device-to-device copies of MIB mebibytes (a "
-                         "known-size kernel for calibrating HBM byte counters) and exit")
+                    help="only run 5 plain device copies and 5 elementwise adds of MIB "
+                         "mebibytes (kernels of known traffic for calibrating the HBM byte "
+                         "counters) and exit")
     return ap.parse_args()
 
 
 def copy_probe(mib):
-    """Five plain copies of `mib` MiB (torch's copy kernel): each reads and
-    writes exactly mib MiB, the reference for FETCH_SIZE / WRITE_SIZE."""
+    """Five plain copies of `mib` MiB (torch's copy kernel: reads and writes
+    mib MiB each) and five elementwise adds c = a + b (reads 2 x mib MiB,
+    writes mib MiB each): the known-traffic references for FETCH_SIZE and
+    WRITE_SIZE."""
     import torch
     n = mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
+    c = torch.empty_like(a)
     for _ in range(5):
         b.copy_(a)
     torch.cuda.synchronize()
+    for _ in range(5):
+        torch.add(a, b, out=c)
+    torch.cuda.synchronize()
     print(json.dumps({"copy_probe_mib": mib, "bytes_read_per_copy": n * 4,
-                      "bytes_written_per_copy": n * 4, "copies": 5}), flush=True)
+                      "bytes_written_per_copy": n * 4, "copies": 5,
+                      "bytes_read_per_add": 2 * n * 4, "bytes_written_per_add": n * 4,
+                      "adds": 5}), flush=True)
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
 
 
 def bench_batched(plain_glups):
@@ -89,7 +110,9 @@ def bench_batched(plain_glups):
     (default_rng(4)), per-grid 16-Gaussian sources (default_rng(4000+g)), FP32
     with FP64 residual, stop at relative residual 1e-6 or 5000 sweeps, residual
     every 50; one launch per pass over all active grids, check intervals
-    replayed as hipGraphs, autotuned depth and tile height."""
+    replayed as hipGraphs, autotuned depth and tile height.  Returns the record
+    and, for the error check, the final states of the three smallest grids and
+    the median one."""
     import numpy as np
     import torch
     import paper_2303_02543_amd as jb
@@ -99,6 +122,8 @@ def bench_batched(plain_glups):
     srcs = [torch.from_numpy(synthetic.batched_source(n, g).astype(np.float32)).to(dev)
             for g, n in enumerate(sizes)]
     zeros = [torch.zeros((n + 2, n + 2), dtype=torch.float32, device=dev) for n in sizes]
+    order = sorted(range(len(sizes)), key=lambda g: sizes[g])
+    picks = order[:3] + [order[len(order) // 2]]
     B = jb.Batch([(n, n) for n in sizes], torch.float32, block=512, device=dev)
     try:
         depth, rows = B.autotune(50)
@@ -115,6 +140,7 @@ def bench_batched(plain_glups):
         sw, rl, st = solve()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        finals = {g: _host(B.get_grid(g)) for g in picks}
     finally:
         B.close()
     updates = float(sum(n * n * k for n, k in zip(sizes, sw)))
@@ -122,15 +148,18 @@ def bench_batched(plain_glups):
     counts = {}
     for v in st:
         counts[jb.STATUS_NAMES[v]] = counts.get(jb.STATUS_NAMES[v], 0) + 1
-    return {
+    rec = {
         "workload": "64 independent 2D 5-point Poisson grids, sides U{257..4097}, FP32, FP64 "
                     "residual every 50, stop at rel 1e-6 or 5000 sweeps",
         "grids": len(sizes), "sum_n2": int(sum(n * n for n in sizes)),
         "cell_updates": updates, "seconds": round(dt, 4), "glups": round(glups, 3),
-        "ratio_vs_plain": round(glups / plain_glups, 4), "t_depth": depth, "rows": rows,
+        "ratio_vs_plain": round(glups / plain_glups, 4) if plain_glups else None,
+        "t_depth": depth, "rows": rows,
         "graph": True, "status_counts": counts,
         "rel_min": min(rl), "rel_max": max(rl),
     }
+    check = {"grids": [(g, sizes[g], int(sw[g]), finals[g]) for g in picks]}
+    return rec, check
 
 
 def bench_adjoint(plain_glups):
@@ -147,9 +176,10 @@ def bench_adjoint(plain_glups):
     n, K, C = 4096, 500, 50
     U0, f, t = synthetic.adjoint_gaussians(n)
     h2 = synthetic.spacing2(n)
-    U0d = torch.from_numpy(U0.astype(np.float32)).to(dev)
-    fd = torch.from_numpy(f.astype(np.float32)).to(dev)
-    td = torch.from_numpy(t.astype(np.float32)).to(dev)
+    U0_32, f_32, t_32 = (a.astype(np.float32) for a in (U0, f, t))
+    U0d = torch.from_numpy(U0_32).to(dev)
+    fd = torch.from_numpy(f_32).to(dev)
+    td = torch.from_numpy(t_32).to(dev)
     s = jb.Solver((n, n), (8, 8), torch.float32, device=dev)
     try:
         def run():
@@ -164,21 +194,26 @@ def bench_adjoint(plain_glups):
             loss.backward()
             torch.cuda.synchronize()
             t2 = time.perf_counter()
-            return t1 - t0, t2 - t1, float(loss)
+            return t1 - t0, t2 - t1, float(loss.detach()), fT.grad, UT.grad
         run()
-        fwd, bwd, L = run()
+        fwd, bwd, L, gf, gU = run()
+        gf, gU = _host(gf), _host(gU)
     finally:
         s.close()
     cells = float(n) * n
-    return {
+    rec = {
         "workload": "adjoint of 1/2||u_K - t||^2, 4096^2 FP32 2D Poisson, K=500, C=50",
         "forward_ms": round(fwd * 1e3, 3), "backward_ms": round(bwd * 1e3, 3),
         "fwd_plus_bwd_over_fwd": round((fwd + bwd) / fwd, 4),
         "forward_glups": round(cells * K / fwd / 1e9, 3),
         "adjoint_glups": round(cells * K / bwd / 1e9, 3),
-        "adjoint_ratio_vs_plain": round(cells * K / bwd / 1e9 / plain_glups, 4),
+        "adjoint_ratio_vs_plain": round(cells * K / bwd / 1e9 / plain_glups, 4)
+        if plain_glups else None,
         "loss": L,
     }
+    check = {"U0": U0_32, "f": f_32, "t": t_32, "h2": h2, "K": K, "loss": L,
+             "grad_f": gf, "grad_U0": gU}
+    return rec, check
 
 
 def bench_poisson3d(plain_glups):
@@ -194,6 +229,7 @@ def bench_poisson3d(plain_glups):
     h2 = synthetic.spacing2(n)
     out = {"workload": "3D 7-point Poisson 512^3, 8x8x8 blocks of 64^3, 200 sweeps, residual "
                        "every 20"}
+    check = {"f": f, "h2": h2, "K": K, "states": {}}
     for name, np_dt, t_dt in (("f32", np.float32, torch.float32), ("f64", np.float64, torch.float64)):
         fd = torch.from_numpy(f.astype(np_dt)).to(dev)
         Ud = torch.from_numpy(U0.astype(np_dt)).to(dev)
@@ -216,18 +252,24 @@ def bench_poisson3d(plain_glups):
             p = s.profile_read(0)
             s.profile(False)
             tuning = s.get_tuning()
+            check["states"][name] = _host(s.get_state())
         finally:
             s.close()
         es = 4 if name == "f32" else 8
         kms = p["ms"] / max(p["launches"], 1)
         d3, z3, f3 = tuning
+        kname = "k_march3d<%s, 1>" % ("float" if name == "f32" else "double")
+        alg = 3 * es * float(n) ** 3
         out[name] = {"glups": round(float(n) ** 3 * K / dt / 1e9, 3),
-                     "zseg": z3, "flags": f3,
+                     "t_depth": d3, "zseg": z3, "flags": f3,
+                     "pass_kernel": kname,
                      "pass_kernel_avg_ms": round(kms, 5),
-                     "pass_kernel_hbm_gbs_alg": round(3 * es * float(n) ** 3 / (kms * 1e-3) / 1e9, 1),
-                     "ratio_vs_plain_2d": round(float(n) ** 3 * K / dt / 1e9 / plain_glups, 4)}
+                     "pass_kernel_hbm_gbs_alg": round(alg / (kms * 1e-3) / 1e9, 1),
+                     "traffic": traffic_for(kname),
+                     "ratio_vs_plain_2d": round(float(n) ** 3 * K / dt / 1e9 / plain_glups, 4)
+                     if plain_glups else None}
         del fd, Ud
-    return out
+    return out, check
 
 
 def bench_plain2d():
@@ -236,7 +278,8 @@ def bench_plain2d():
     order of the paper's proxy) and the fused pass at depth 1 (halo cells read
     from their owning blocks), FP32 and FP64.  HBM figures are algorithmic
     bytes (state read + source read + state write per cell) over the sweep
-    kernel's own time (HIP events on the solver's stream)."""
+    kernel's own time (HIP events on the solver's stream).  Every form starts
+    from u_0 = 0 and runs 2K sweeps (K untimed, K timed)."""
     import numpy as np
     import torch
     import paper_2303_02543_amd as jb
@@ -246,15 +289,22 @@ def bench_plain2d():
     f64 = synthetic.gaussian_sum(n, 2, 2)
     h2 = synthetic.spacing2(n)
     out = {"workload": "2D 5-point Poisson %dx%d, 16x16 blocks, %d plain sweeps" % (n, n, K)}
+    check = {"f": f64, "h2": h2, "K": 2 * K, "states": {}}
     for name, np_dt, t_dt in (("f32", np.float32, torch.float32), ("f64", np.float64, torch.float64)):
         es = 4 if name == "f32" else 8
+        tname = "float" if name == "f32" else "double"
         s = jb.Solver((n, n), BLOCKS, t_dt, device=dev)
         try:
             s.set_source(torch.from_numpy(f64.astype(np_dt)).to(dev), h2)
-            s.set_state(torch.zeros((n + 2, n + 2), dtype=t_dt, device=dev))
+            zero = torch.zeros((n + 2, n + 2), dtype=t_dt, device=dev)
             rec = {}
-            for form, flags in (("explicit_halo", jb.JACOBI_FLAG_EXPLICIT_HALO), ("fused", 0)):
+            finals = []
+            for form, flags, kname in (
+                    ("explicit_halo", jb.JACOBI_FLAG_EXPLICIT_HALO,
+                     "k_sweep_tile<%s, true>" % tname),
+                    ("fused", 0, "k_march2d<%s, 1, 1>" % tname)):
                 s.set_tuning(1, 0, flags)
+                s.set_state(zero)
                 s.sweep(K)
                 torch.cuda.synchronize()
                 s.profile(True)
@@ -264,16 +314,21 @@ def bench_plain2d():
                 dt = time.perf_counter() - t0
                 p = s.profile_read(0)
                 s.profile(False)
+                finals.append(_host(s.get_state()))
                 kms = p["ms"] / max(p["launches"], 1)
                 gbs = 3 * es * float(n) ** 2 / (kms * 1e-3) / 1e9
                 rec[form] = {"glups": round(float(n) ** 2 * K / dt / 1e9, 3),
+                             "sweep_kernel": kname,
                              "sweep_kernel_avg_ms": round(kms, 5),
                              "sweep_kernel_hbm_gbs_alg": round(gbs, 1),
-                             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+                             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                             "traffic": traffic_for(kname)}
+            rec["forms_bit_identical"] = bool(np.array_equal(finals[0], finals[1]))
             out[name] = rec
+            check["states"][name] = finals[1]
         finally:
             s.close()
-    return out
+    return out, check
 
 
 def bench_overdecomposition():
@@ -281,7 +336,9 @@ def bench_overdecomposition():
     sweeps (exchange, then block-local update) of the 8192^2 FP32 Poisson
     grid in 4x4 ... 64x64 blocks, without and with the overlap of each slab's
     face sends with the next slab's sweep (JACOBI_FLAG_OVERLAP).  Whole-sweep
-    GLUP/s, exchange included."""
+    GLUP/s, exchange included.  Every point starts from u_0 = 0 and runs 55
+    sweeps; the final states of all points and both orders must be
+    bit-identical (any decomposition gives the monolithic result)."""
     import numpy as np
     import torch
     import paper_2303_02543_amd as jb
@@ -289,47 +346,72 @@ def bench_overdecomposition():
     dev = torch.device("cuda:0")
     n, K = N, 50
     f = torch.from_numpy(synthetic.gaussian_sum(n, 2, 2).astype(np.float32)).to(dev)
+    zero = torch.zeros((n + 2, n + 2), dtype=torch.float32, device=dev)
     rows = []
+    ref = None
+    same = True
     for nb in (4, 8, 16, 32, 64):
         s = jb.Solver((n, n), (nb, nb), torch.float32, device=dev)
         try:
             s.set_source(f, synthetic.spacing2(n))
-            s.set_state(torch.zeros((n + 2, n + 2), dtype=torch.float32, device=dev))
             rec = {"blocks": [nb, nb]}
             for name, fl in (("explicit_halo", jb.JACOBI_FLAG_EXPLICIT_HALO),
                              ("overlapped", jb.JACOBI_FLAG_EXPLICIT_HALO | jb.JACOBI_FLAG_OVERLAP)):
                 s.set_tuning(1, 0, fl)
+                s.set_state(zero)
                 s.sweep(5)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 s.sweep(K)
                 torch.cuda.synchronize()
                 rec[name + "_glups"] = round(float(n) ** 2 * K / (time.perf_counter() - t0) / 1e9, 2)
+                fin = s.get_state()
+                if ref is None:
+                    ref = fin
+                else:
+                    same = same and bool(torch.equal(fin, ref))
             rows.append(rec)
         finally:
             s.close()
     return {"workload": "2D 5-point Poisson %dx%d FP32, %d explicit-halo sweeps per point" % (n, n, K),
-            "points": rows}
+            "points": rows, "states_bit_identical_across_points": same}, None
+
+
+PAPER_DOMAIN = (1024, 1024, 768)
+PAPER_TILE = (48, 64, 64)  # the source is a seeded U[-1,1) tile repeated over the domain
+PAPER_WINDOWS = [((0, 64), (0, 64), (0, 48)),          # domain corner
+                 ((480, 544), (500, 564), (370, 400)),  # across block seams, inside
+                 ((960, 1024), (990, 1024), (740, 768))]  # far corner
+
+
+def paper_source_tile():
+    import synthetic
+    return synthetic.uniform(PAPER_TILE, 13, -1.0, 1.0)
 
 
 def bench_paper_domain():
     """The paper's Jacobi3D domain (Section 4.3), 1024 x 1024 x 768, 7-point
     Poisson in 16 x 16 x 12 blocks of 64^3, a fixed number of sweeps as in the
-    paper (no residual), FP32 and FP64, autotuned 3D schedule."""
+    paper (no residual), FP32 and FP64, autotuned 3D schedule.  Starts from
+    u_0 = 0 and runs 42 sweeps (2 untimed, 40 timed); returns three windows of
+    the final state for the error check."""
     import numpy as np
     import torch
     import paper_2303_02543_amd as jb
     import synthetic
     dev = torch.device("cuda:0")
-    nx, ny, nz, K = 1024, 1024, 768, 40
+    nx, ny, nz = PAPER_DOMAIN
+    K = 40
     out = {"workload": "3D 7-point Poisson %dx%dx%d (the paper's Jacobi3D domain), 16x16x12 "
                        "blocks of 64^3, %d sweeps" % (nx, ny, nz, K)}
-    tile = synthetic.uniform((48, 64, 64), 13, -1.0, 1.0)
+    tile = paper_source_tile()
+    reps = (nz // PAPER_TILE[0], ny // PAPER_TILE[1], nx // PAPER_TILE[2])
+    check = {"K": K + 2, "h2": synthetic.spacing2(nx), "windows": {}}
     for name, np_dt, t_dt in (("f32", np.float32, torch.float32), ("f64", np.float64, torch.float64)):
         s = jb.Solver((nx, ny, nz), (16, 16, 12), t_dt, device=dev)
         try:
             s.autotune(10, with_source=True)
-            s.set_source(torch.from_numpy(np.tile(tile.astype(np_dt), (16, 16, 16))).to(dev),
+            s.set_source(torch.from_numpy(np.tile(tile.astype(np_dt), reps)).to(dev),
                          synthetic.spacing2(nx))
             s.set_state(torch.zeros((nz + 2, ny + 2, nx + 2), dtype=t_dt, device=dev))
             s.sweep(2)
@@ -342,41 +424,155 @@ def bench_paper_domain():
             glups = float(nx) * ny * nz * K / dt / 1e9
             d3, z3, f3 = s.get_tuning()
             out[name] = {"glups": round(glups, 2), "hbm_gbs_alg": round(glups * 3 * es, 1),
-                         "zseg": z3, "flags": f3}
+                         "t_depth": d3, "zseg": z3, "flags": f3}
+            full = s.get_state()
+            check["windows"][name] = [
+                _host(full[z0 + 1:z1 + 1, y0 + 1:y1 + 1, x0 + 1:x1 + 1])
+                for (x0, x1), (y0, y1), (z0, z1) in PAPER_WINDOWS]
+            del full
         finally:
             s.close()
-    return out
+    return out, check
 
 
-def source_hash(path):
+def _src_hash(path):
     with open(path, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def traffic_for(kernel_name, launches_alg_bytes):
-    """HBM bytes per launch from committed rocprofv3 counter runs, or None when
-    they are missing or were taken on a different kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
+def traffic_for(kernel_name):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summaries (profiles/traffic_*.json), or None when none covers it or the
+    kernel's source has changed since the counters were taken."""
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
+        try:
+            with open(path) as fh:
+                rec = json.load(fh)
+        except (OSError, ValueError):
+            continue
+        k = rec.get("kernels", {}).get(kernel_name)
+        if not k:
+            continue
+        src = os.path.join(ROOT, rec.get("source", ""))
+        if not os.path.isfile(src) or rec.get("source_sha256_16") != _src_hash(src):
+            return None
+        return k.get("hbm_bytes_per_launch")
+    return None
+
+
+def _cpu_model():
     try:
-        with open(TRAFFIC_FILE) as fh:
-            rec = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if rec.get("source_sha256_16") != source_hash(SWEEP_SOURCE):
-        return None
-    k = rec.get("kernels", {}).get(kernel_name)
-    if not k:
-        return None
-    return k.get("hbm_bytes_per_launch")
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
-def cpu_baseline(U0_np, f_np, h2, target_seconds, full_max_seconds, gpu_final):
-    """Time the FP64 oracle on the host's cores.  When the whole workload
-    (SWEEPS sweeps, a residual every CHECK_EVERY) is estimated to fit in
-    full_max_seconds it is run in full and the GPU's final FP32 state is
-    compared with it (max-abs error and max-abs error / max-abs value over the
-    interior); otherwise a bounded sample of sweeps on the full grid is timed."""
+def _err(got, want, interior=True):
+    """max-abs error of got against the FP64 reference, and that over the
+    reference's max-abs value (norm-wise relative error)."""
+    import numpy as np
+    g = np.asarray(got, dtype=np.float64)
+    w = np.asarray(want, dtype=np.float64)
+    if interior:
+        sl = (slice(1, -1),) * g.ndim
+        g, w = g[sl], w[sl]
+    e = float(np.max(np.abs(g - w))) if g.size else 0.0
+    m = float(np.max(np.abs(w))) if w.size else 0.0
+    return {"max_abs": e, "rel": e / m if m > 0 else e, "bound": REL_BOUND}
+
+
+def form_errors(checks):
+    """Error of every form's result against the FP64 oracle (CPU-baseline
+    leg: the only part of the benchmark that runs the oracle)."""
+    import numpy as np
+    import oracle
+    import synthetic
+    out = {}
+    c = checks.get("plain2d")
+    if c:
+        n = c["f"].shape[0]
+        b = oracle.scale_source(c["f"].astype(np.float32).astype(np.float64), c["h2"], np.float64)
+        ref = oracle.sweep(np.zeros((n + 2, n + 2)), b, c["K"])
+        b64 = oracle.scale_source(c["f"], c["h2"], np.float64)
+        ref64 = oracle.sweep(np.zeros((n + 2, n + 2)), b64, c["K"])
+        out["plain2d"] = {"f32": _err(c["states"]["f32"], ref),
+                          "f64": _err(c["states"]["f64"], ref64),
+                          "vs": "FP64 oracle, whole grid, %d sweeps from u_0 = 0" % c["K"]}
+    c = checks.get("poisson3d")
+    if c:
+        n = c["f"].shape[0]
+        U0 = np.zeros((n + 2,) * 3)
+        r = {}
+        for name, dt in (("f32", np.float32), ("f64", np.float64)):
+            b = oracle.scale_source(c["f"].astype(dt).astype(np.float64), c["h2"], np.float64)
+            r[name] = _err(c["states"][name], oracle.sweep(U0, b, c["K"]))
+        r["vs"] = "FP64 oracle, whole grid, %d sweeps" % c["K"]
+        out["poisson3d"] = r
+    c = checks.get("batched")
+    if c:
+        per = []
+        for g, n, sw, state in c["grids"]:
+            f = synthetic.batched_source(n, g).astype(np.float32).astype(np.float64)
+            b = oracle.scale_source(f, synthetic.spacing2(n), np.float64)
+            e = _err(state, oracle.sweep(np.zeros((n + 2, n + 2)), b, sw))
+            e.update({"grid": g, "n": n, "sweeps": sw})
+            per.append(e)
+        out["batched"] = {"grids": per, "max_rel": max(p["rel"] for p in per),
+                          "vs": "FP64 oracle on the three smallest grids and the median one, "
+                                "same sweep count"}
+    c = checks.get("adjoint")
+    if c:
+        L, gf, gU = oracle.gradients2d(c["U0"].astype(np.float64), c["f"].astype(np.float64),
+                                       c["h2"], c["t"].astype(np.float64), c["K"])
+        ring = np.ones(gU.shape, dtype=bool)
+        ring[1:-1, 1:-1] = False
+        out["adjoint"] = {
+            "dL_df": _err(c["grad_f"], gf, interior=False),
+            "dL_dg": _err(c["grad_U0"][ring], gU[ring], interior=False),
+            "dL_du0": _err(c["grad_U0"][1:-1, 1:-1], gU[1:-1, 1:-1], interior=False),
+            "loss_rel": abs(c["loss"] - L) / abs(L),
+            "vs": "FP64 oracle adjoint (same FP32-rounded inputs)"}
+    c = checks.get("paper_domain_3d")
+    if c:
+        # each window from a copy of the region grown by K nodes per side (by
+        # then nothing outside it can reach the window), computed by the
+        # oracle; the grown region's outer layer acts as a fixed ring
+        tile = paper_source_tile()
+        nx, ny, nz = PAPER_DOMAIN
+        K = c["K"]
+        r = {}
+        for name, dt in (("f32", np.float32), ("f64", np.float64)):
+            errs = []
+            for wi, ((x0, x1), (y0, y1), (z0, z1)) in enumerate(PAPER_WINDOWS):
+                lo = [max(0, v - K) for v in (x0, y0, z0)]
+                hi = [min(m, v + K) for v, m in zip((x1, y1, z1), (nx, ny, nz))]
+                zs, ys, xs = (np.arange(lo[a], hi[a]) for a in (2, 1, 0))
+                f = tile[np.ix_(zs % PAPER_TILE[0], ys % PAPER_TILE[1], xs % PAPER_TILE[2])]
+                b = oracle.scale_source(f.astype(dt).astype(np.float64), c["h2"], np.float64)
+                U = np.zeros(tuple(len(a) + 2 for a in (zs, ys, xs)))
+                ref = oracle.sweep(U, b, K)
+                win = ref[1 + z0 - lo[2]:1 + z1 - lo[2], 1 + y0 - lo[1]:1 + y1 - lo[1],
+                          1 + x0 - lo[0]:1 + x1 - lo[0]]
+                errs.append(_err(c["windows"][name][wi], win, interior=False))
+            worst = max(errs, key=lambda e: e["rel"])
+            r[name] = dict(worst, windows=len(errs))
+        r["vs"] = ("FP64 oracle on %d windows (domain corner, block seams inside, far "
+                   "corner), %d sweeps" % (len(PAPER_WINDOWS), K))
+        out["paper_domain_3d"] = r
+    return out
+
+
+def cpu_baseline(U0_np, f_np, h2, target_seconds, full_max_seconds, gpu_final, checks):
+    """Time the FP64 oracle on the host's cores (and on one thread).  When the
+    whole workload (SWEEPS sweeps, a residual every CHECK_EVERY) is estimated
+    to fit in full_max_seconds it is run in full and the GPU's final FP32
+    state is compared with it (max-abs error and max-abs error / max-abs value
+    over the interior); otherwise a bounded sample of sweeps on the full grid
+    is timed.  Then every form's result is checked against the FP64 oracle."""
     import numpy as np
     import oracle
     U = U0_np.astype(np.float64)
@@ -390,7 +586,8 @@ def cpu_baseline(U0_np, f_np, h2, target_seconds, full_max_seconds, gpu_final):
     oracle.sweep(U, b, 12)
     per_sweep = max((time.perf_counter() - t0 - t2) / 10, 1e-6)
     cells = float(N) * N
-    out = {"unit": "GLUP/s", "cores": oracle.num_threads(), "kind": "oracle"}
+    out = {"unit": "GLUP/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
     if per_sweep * SWEEPS <= full_max_seconds:
         t0 = time.perf_counter()
         res = [oracle.residual(U, b)]
@@ -408,19 +605,51 @@ def cpu_baseline(U0_np, f_np, h2, target_seconds, full_max_seconds, gpu_final):
         oi = U[1:-1, 1:-1]
         err = float(np.max(np.abs(gi - oi)))
         out["error_vs_fp64_oracle"] = {
-            "max_abs": err, "rel": err / float(np.max(np.abs(oi))), "bound": 1e-5,
+            "max_abs": err, "rel": err / float(np.max(np.abs(oi))), "bound": REL_BOUND,
             "oracle_final_residual": res[-1]}
-        return out
-    k = int(max(2, min(200, target_seconds / max(per_sweep, 1e-6))))
-    t0 = time.perf_counter()
-    U = oracle.sweep(U, b, k)
-    r = oracle.residual(U, b)
-    dt = time.perf_counter() - t0
-    out["value"] = round(cells * k / dt / 1e9, 4)
-    out["sample"] = ("FP64 oracle on the full %dx%d grid: %d sweeps + 1 residual (%.1f s)"
-                     % (N, N, k, dt))
-    out["residual_check"] = r if math.isfinite(r) else None
+    else:
+        k = int(max(2, min(200, target_seconds / max(per_sweep, 1e-6))))
+        t0 = time.perf_counter()
+        U = oracle.sweep(U, b, k)
+        r = oracle.residual(U, b)
+        dt = time.perf_counter() - t0
+        out["value"] = round(cells * k / dt / 1e9, 4)
+        out["sample"] = ("FP64 oracle on the full %dx%d grid: %d sweeps + 1 residual (%.1f s)"
+                         % (N, N, k, dt))
+        out["residual_check"] = r if math.isfinite(r) else None
+    # one thread: a short sample of sweeps on the full grid
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        U1 = U0_np.astype(np.float64)
+        oracle.sweep(U1, b, 1)
+        t0 = time.perf_counter()
+        oracle.sweep(U1, b, 12)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    out["one_thread"] = {"value": round(cells * 12 / dt1 / 1e9, 4),
+                         "sample": "FP64 oracle, 1 thread, 12 sweeps of the full %dx%d grid "
+                                   "(%.1f s, grid copy included)" % (N, N, dt1)}
+    if checks:
+        t0 = time.perf_counter()
+        out["form_errors"] = form_errors(checks)
+        out["form_errors_seconds"] = round(time.perf_counter() - t0, 1)
     return out
+
+
+def run_form(name, plain_glups):
+    if name == "batched":
+        return bench_batched(plain_glups)
+    if name == "adjoint":
+        return bench_adjoint(plain_glups)
+    if name == "poisson3d":
+        return bench_poisson3d(plain_glups)
+    if name == "plain2d":
+        return bench_plain2d()
+    if name == "overdecomposition":
+        return bench_overdecomposition()
+    return bench_paper_domain()
 
 
 def main():
@@ -446,6 +675,11 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+
+    if args.only:
+        rec, _ = run_form(args.only, None)
+        print(json.dumps({"form": args.only, "record": rec}), flush=True)
+        return
 
     # inputs: drawn in FP64, rounded once to FP32, resident in HBM
     f64 = synthetic.gaussian_sum(N, 2, 2)
@@ -474,7 +708,7 @@ def main():
     def step():
         s.set_source(f_dev, h2)            # scaled source into the blocks
         s.set_state(U0_dev)                # scatter + halo fill
-        s.solve(SWEEPS, CHECK_EVERY, res)  # sweeps, halo exchange, residuals
+        s.solve(SWEEPS, CHECK_EVERY, res)  # sweeps, residuals, halo refresh
         s.get_state(U_out)                 # gather
 
     for _ in range(args.warmup):
@@ -505,13 +739,13 @@ def main():
     hbm_gbs = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     alu_tops = flops_per_launch / (avg_ms * 1e-3) / 1e12
     if flags & jb.JACOBI_FLAG_EXPLICIT_HALO:
-        kname = "k_sweep_local<float, true>"
+        kname = "k_sweep_tile<float, true>"
     else:
         # Poisson pass kernel of depth d_dom and its prefetch distance; the
         # traffic record aggregates its two residual variants
         kname = "k_march2d<float, %d, %d, 1>" % (
             d_dom, 3 if flags & jb.JACOBI_FLAG_DEEP_PREFETCH else 1)
-    traffic = traffic_for(kname, bytes_per_launch)
+    traffic = traffic_for(kname)
     hbm_frac = hbm_gbs / HBM_PEAK_GBS
     alu_frac = alu_tops / ALU_PEAK_TOPS
     if hbm_frac >= alu_frac:
@@ -528,7 +762,9 @@ def main():
         "alg_bytes_per_launch": bytes_per_launch,
         "alg_flops_per_launch": flops_per_launch,
         "hbm_gbs_alg": round(hbm_gbs, 1),
+        "hbm_frac_alg": round(hbm_frac, 4),
         "alu_tops_alg": round(alu_tops, 3),
+        "alu_frac": round(alu_frac, 4),
         "kernel_share_of_step": round(tot["ms"] / (ms_per_step * args.steps), 4),
     })
 
@@ -562,16 +798,22 @@ def main():
         "residual_ratio": float(res[-1].item() / res[0].item()),
     }
     s.close()
+    checks = {}
     if not args.no_forms:
-        out["batched"] = bench_batched(glups)
-        out["adjoint"] = bench_adjoint(glups)
-        out["poisson3d"] = bench_poisson3d(glups)
-        out["plain2d"] = bench_plain2d()
-        out["overdecomposition"] = bench_overdecomposition()
-        out["paper_domain_3d"] = bench_paper_domain()
+        for name in FORMS:
+            rec, chk = run_form(name, glups)
+            out[name] = rec
+            if chk is not None:
+                checks[name] = chk
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(U0_np, f32, h2, args.cpu_seconds,
-                                           args.cpu_full_seconds, U_out.cpu().numpy())
+        cb = cpu_baseline(U0_np, f32, h2, args.cpu_seconds, args.cpu_full_seconds,
+                          U_out.cpu().numpy(), checks)
+        out["cpu_baseline"] = cb
+        # each form's record carries its error, computed above by the oracle
+        for name, e in cb.get("form_errors", {}).items():
+            out[name]["error_vs_fp64_oracle"] = e
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -67,6 +67,8 @@ def lib():
         L.orc_adjoint2d_f64.argtypes = [I64, I64, I64, P, P, P, P]
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        L.orc_set_num_threads.restype = None
         _LIB = L
     return _LIB
 
@@ -74,6 +76,11 @@ def lib():
 def num_threads():
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n):
+    """Threads of later oracle calls (results do not depend on the count)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def _suffix(dtype):

@@ -36,6 +36,9 @@
 /* Threads an OpenMP region of the oracle uses. */
 int orc_num_threads(void) { return omp_get_max_threads(); }
 
+/* Set the threads of later OpenMP regions (results never depend on it). */
+void orc_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
 /*
  * Reverse-mode derivative of L = 1/2 * sum_interior (u_K - t)^2 through K
  * sweeps of the 2D iteration (not in the paper; the differentiable form of the
