@@ -275,8 +275,8 @@ def bench_poisson3d(plain_glups):
 def bench_plain2d():
     """Plain sweeps (one sweep per kernel) of the 8192^2 Poisson grid in 16x16
     blocks: the block-local sweep after an explicit halo exchange (the step
-    order of the paper's proxy) and the fused pass at depth 1 (halo cells read
-    from their owning blocks), FP32 and FP64.  HBM figures are algorithmic
+    order of the paper's proxy) and the fused tile sweep (cells outside a
+    block read from their owning blocks, no exchange), FP32 and FP64.  HBM figures are algorithmic
     bytes (state read + source read + state write per cell) over the sweep
     kernel's own time (HIP events on the solver's stream).  Every form starts
     from u_0 = 0 and runs 2K sweeps (K untimed, K timed)."""
@@ -301,8 +301,8 @@ def bench_plain2d():
             finals = []
             for form, flags, kname in (
                     ("explicit_halo", jb.JACOBI_FLAG_EXPLICIT_HALO,
-                     "k_sweep_tile<%s, true>" % tname),
-                    ("fused", 0, "k_march2d<%s, 1, 1>" % tname)):
+                     "k_sweep_tile<%s, true, false>" % tname),
+                    ("fused", 0, "k_sweep_tile<%s, true, true>" % tname)):
                 s.set_tuning(1, 0, flags)
                 s.set_state(zero)
                 s.sweep(K)

@@ -140,6 +140,14 @@ int plan(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, Geom *
                           ((size_t)g->n[2] / kMinRows + 2);
         if (c3 > cap) cap = c3;
     }
+    if (ndim == 2) {
+        // 2D tile sweep at depth 1: one partial per wave, 4 per work item of
+        // (block, 64 x 16-byte column chunk, 4-row tile)
+        const size_t chunk = 64 * (16 / es);
+        const size_t ct = 4 * nblk * (((size_t)g->e[0] + chunk - 1) / chunk) *
+                          (((size_t)g->e[1] + 3) / 4);
+        if (ct > cap) cap = ct;
+    }
     if (cap < (size_t)jac::kResidualGroups) cap = jac::kResidualGroups;
     l->part_cap = cap;
     l->off_part = off;
@@ -433,7 +441,7 @@ int do_sweep(jacobi_t h, int64_t n, double *res_first, bool sync_halos = true) {
             int rc = prof_begin(h);
             if (rc) return rc;
             HIP_TRY(jac::launch_sweep_local<R>(h->g, h->u[h->cur], h->u[h->cur ^ 1], b, h->stream,
-                                               h->rows),
+                                               h->rows, 0, -1, h->flags & JACOBI_FLAG_NT_STORES),
                     "sweep launch");
             rc = prof_end(h, 1);
             if (rc) return rc;
@@ -453,6 +461,32 @@ int do_sweep(jacobi_t h, int64_t n, double *res_first, bool sync_halos = true) {
         const int64_t passes = (left + depth - 1) / depth;
         const int t = pick_depth(h->dtype, (int)((left + passes - 1) / passes));
         double *part = nullptr;
+        if (t == 1) {
+            // one sweep per pass: the tile kernel, reading block-edge
+            // neighbours from their owning blocks
+            if (first && res_first) {
+                const int64_t nw = jac::sweep_tile_partials<R>(h->g, 0);
+                if (nw < 0 || (size_t)nw > h->lay.part_cap)
+                    return fail(JACOBI_E_INVAL, "partials overflow");
+                part = h->partials;
+            }
+            int rc = prof_begin(h);
+            if (rc) return rc;
+            int64_t nwork = 0;
+            HIP_TRY(jac::launch_sweep2d_tile_fused<R>(h->g, h->u[h->cur], h->u[h->cur ^ 1], b, part,
+                                                      0, h->stream, &nwork,
+                                                      h->flags & JACOBI_FLAG_NT_STORES),
+                    "sweep launch");
+            rc = prof_end(h, 1);
+            if (rc) return rc;
+            if (part)
+                HIP_TRY(jac::launch_residual_final(part, (int)nwork, res_first, h->stream),
+                        "residual launch");
+            first = false;
+            h->cur ^= 1;
+            left -= 1;
+            continue;
+        }
         if (first && res_first) {
             const int64_t nw = jac::march2d_work_items<R>(h->g, t, rows);
             if (nw < 0 || (size_t)nw > h->lay.part_cap)

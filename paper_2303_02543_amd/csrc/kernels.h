@@ -28,10 +28,24 @@ template <typename R>
 hipError_t launch_halo_exchange(const Geom &g, void *s, hipStream_t st);
 
 // One sweep of blocks b0 .. b1-1 (b1 < 0: to the last block) from their own
-// storage (halos must be current).  2D: rg rows per work item (0: a default).
+// storage (halos must be current).  2D: rg rows per work item (0: a default);
+// nt != 0: non-temporal output stores (2D tiles).
 template <typename R>
 hipError_t launch_sweep_local(const Geom &g, const void *uin, void *uout, const void *b,
-                              hipStream_t st, int rg = 0, int64_t b0 = 0, int64_t b1 = -1);
+                              hipStream_t st, int rg = 0, int64_t b0 = 0, int64_t b1 = -1,
+                              int nt = 0);
+// One 2D sweep of the whole grid by the tile kernel, reading the cells just
+// outside each block from the neighbouring blocks that own them (no halo
+// exchange needed; the stored halos are not refreshed).  rg: rows per tile
+// (0: the default).  If res is not NULL, the FP64 residual of the input
+// state is summed into one partial per wave, res[0 .. *nwork).
+template <typename R>
+hipError_t launch_sweep2d_tile_fused(const Geom &g, const void *uin, void *uout, const void *b,
+                                     double *res, int rg, hipStream_t st, int64_t *nwork,
+                                     int nt = 0);
+// Residual partials of one launch_sweep2d_tile_fused launch.
+template <typename R>
+int64_t sweep_tile_partials(const Geom &g, int rg);
 // Face sends of blocks b0 .. b1-1: each block's edge cells into the halos of
 // its face neighbours (all blocks together: the same as launch_halo_exchange).
 template <typename R>

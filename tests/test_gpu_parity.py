@@ -151,12 +151,36 @@ def test_2d_residuals_and_states(device, case, flags):
     for src in (f, None):
         want, b = oracle_run(U0, src, h2, K, np.float32)
         ores, _ = oracle_residuals(np.asarray(U0, dtype=np.float32), b, K, 4)
-        for depth in (3, jb.jacobi_max_depth(2, jb.JACOBI_F32)):
+        for depth in (1, 3, jb.jacobi_max_depth(2, jb.JACOBI_F32)):
             say("2d residuals case=%s depth=%d flags=%d source=%s"
                 % (case, depth, flags, src is not None))
             got, res = run_device(U0, src, h2, K, (bx, by), np.float32, device, depth=depth,
                                   flags=flags, check_every=4)
             assert_bits(got, want, "2d %s depth %d flags %d" % (case, depth, flags))
+            np.testing.assert_allclose(res, ores, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("case", CASES_2D)
+def test_2d_plain_sweep_residuals(device, dtype, case):
+    """One sweep per pass (the tile kernel reading block-edge neighbours from
+    their owning blocks) with the residual every 3 sweeps folded into it:
+    states bit-exact with the oracle, residuals within 1e-12; the explicit
+    halo order agrees bit for bit."""
+    import paper_2303_02543_amd as jb
+    nx, ny, bx, by, K = case
+    U0 = RNG.uniform(0, 1, (ny + 2, nx + 2))
+    f = RNG.standard_normal((ny, nx)) * 100
+    h2 = synthetic.spacing2(max(nx, ny))
+    for src in (f, None):
+        want, b = oracle_run(U0, src, h2, K, dtype)
+        ores, _ = oracle_residuals(np.asarray(U0, dtype=dtype), b, K, 3)
+        for flags in (0, jb.JACOBI_FLAG_EXPLICIT_HALO):
+            say("2d plain residuals case=%s dtype=%s flags=%d source=%s"
+                % (case, np.dtype(dtype).name, flags, src is not None))
+            got, res = run_device(U0, src, h2, K, (bx, by), dtype, device, depth=1, flags=flags,
+                                  check_every=3)
+            assert_bits(got, want, "2d plain %s flags %d" % (case, flags))
             np.testing.assert_allclose(res, ores, rtol=1e-12, atol=0)
 
 
