@@ -265,7 +265,7 @@ def bench_poisson3d(plain_glups):
                      "pass_kernel": kname,
                      "pass_kernel_avg_ms": round(kms, 5),
                      "pass_kernel_hbm_gbs_alg": round(alg / (kms * 1e-3) / 1e9, 1),
-                     "traffic": traffic_for(kname),
+                     "traffic": traffic_for("%s zseg=%d" % (kname, z3)),
                      "ratio_vs_plain_2d": round(float(n) ** 3 * K / dt / 1e9 / plain_glups, 4)
                      if plain_glups else None}
         del fd, Ud
