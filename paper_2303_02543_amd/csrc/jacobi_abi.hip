@@ -135,8 +135,9 @@ int plan(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, Geom *
     size_t cap = ((size_t)g->n[0] / 32 + 2) * ((size_t)g->n[1] * g->n[2] / kMinRows + 2);
     if (ndim == 3) {
         // 3D pass: 4 partials (one per wave) per work item of (strip of
-        // >= 32 columns, 16 rows, z segment of >= kMinRows planes)
-        const size_t c3 = ((size_t)g->n[0] / 32 + 2) * 4 * ((size_t)g->n[1] / 16 + 2) *
+        // >= 24 output columns, >= 10 output rows, z segment of >= kMinRows
+        // planes), the smallest tiles of any depth
+        const size_t c3 = ((size_t)g->n[0] / 24 + 2) * 4 * ((size_t)g->n[1] / 10 + 2) *
                           ((size_t)g->n[2] / kMinRows + 2);
         if (c3 > cap) cap = c3;
     }
@@ -240,12 +241,13 @@ int balanced_rows(const jacobi_s *h, int depth, int mode, int rounds, int deep) 
     return lo;
 }
 
-// Defaults before any tuning: the fastest schedule measured on MI355X for a
-// 2D FP32 8192^2 grid with a residual every 50 sweeps (depth 13: passes of
+// Defaults before any tuning: the fastest schedules measured on MI355X for
+// a 2D FP32 8192^2 grid with a residual every 50 sweeps (depth 13: passes of
 // 13, 13, 12, 12), with a tile height that fills the GPU in one round of
-// resident waves; one sweep per pass in 3D.
+// resident waves, and for a 512^3 grid in 64^3 blocks (depth 4, the deepest
+// 3D pass: 836 / 475 GLUP/s in FP32 / FP64 against 381 / 190 at depth 1).
 int default_depth(const jacobi_s *h) {
-    if (h->g.ndim == 3) return 1;
+    if (h->g.ndim == 3) return 4;
     return h->dtype == JACOBI_F32 ? 13 : 4;
 }
 
@@ -266,7 +268,7 @@ int default_rows(const jacobi_s *h) {
 }
 
 int max_depth(int ndim, int dtype) {
-    if (ndim == 3) return 1;
+    if (ndim == 3) return jac::march3d_max_depth();
     const int *list;
     const int n = jac::march2d_depths(dtype, &list);
     return list[n - 1];
@@ -310,7 +312,12 @@ int do_halo(jacobi_t h) {
     return JACOBI_OK;
 }
 
-int zseg_of(const jacobi_s *h) { return h->rows > 0 ? h->rows : 32; }
+// z planes per work item of the 3D pass: 32 (FP32) / 64 (FP64) measured
+// fastest at depth 4 on 512^3 (16 .. 128 tried; shorter segments repeat the
+// 2(T-1) warm-up planes more often, longer ones leave too few work items).
+int zseg_of(const jacobi_s *h) {
+    return h->rows > 0 ? h->rows : h->dtype == JACOBI_F32 ? 32 : 64;
+}
 
 template <typename R>
 int do_residual(jacobi_t h, double *out) {
@@ -407,24 +414,32 @@ int do_sweep(jacobi_t h, int64_t n, double *res_first, bool sync_halos = true) {
     const bool explicit_halo = (h->flags & JACOBI_FLAG_EXPLICIT_HALO) != 0 ||
                                (h->g.ndim == 2 && !march_fits(h->g, h->dtype));
     if (h->g.ndim == 3 && !explicit_halo && n > 0) {
-        // fused 3D passes, one sweep each; the first also sums the residual
+        // fused 3D passes of up to `depth` sweeps each, split as evenly as
+        // possible; the first also sums the residual of its input
         const int zseg = zseg_of(h);
-        for (int64_t k = 0; k < n; ++k) {
-            double *part = (k == 0 && res_first) ? h->partials : nullptr;
-            if (part && (size_t)jac::march3d_work_items<R>(h->g, zseg) > h->lay.part_cap)
+        const int depth = h->depth > 0 ? h->depth : default_depth(h);
+        int64_t left = n;
+        bool first = true;
+        while (left > 0) {
+            const int64_t passes = (left + depth - 1) / depth;
+            const int t = (int)((left + passes - 1) / passes);
+            double *part = (first && res_first) ? h->partials : nullptr;
+            if (part && (size_t)jac::march3d_work_items<R>(h->g, zseg, t) > h->lay.part_cap)
                 return fail(JACOBI_E_INVAL, "partials overflow");
             int rc = prof_begin(h);
             if (rc) return rc;
             int64_t nwork = 0;
             HIP_TRY(jac::launch_march3d<R>(h->g, h->u[h->cur], h->u[h->cur ^ 1], b, part, zseg,
-                                           h->stream, &nwork, h->flags & JACOBI_FLAG_NT_STORES),
+                                           h->stream, &nwork, h->flags & JACOBI_FLAG_NT_STORES, t),
                     "sweep launch");
-            rc = prof_end(h, 1);
+            rc = prof_end(h, t);
             if (rc) return rc;
             if (part)
                 HIP_TRY(jac::launch_residual_final(part, (int)nwork, res_first, h->stream),
                         "residual launch");
+            first = false;
             h->cur ^= 1;
+            left -= t;
         }
         if (sync_halos)
             HIP_TRY(jac::launch_halo_exchange<R>(h->g, h->u[h->cur], h->stream),
@@ -941,7 +956,7 @@ int jacobi_get_tuning(jacobi_t h, int *t_depth, int *rows, int *flags) {
     if (rc) return rc;
     if (!t_depth || !rows || !flags) return fail(JACOBI_E_INVAL, "output pointers must not be NULL");
     *t_depth = h->depth > 0 ? h->depth : default_depth(h);
-    *rows = h->rows > 0 ? h->rows : default_rows(h);
+    *rows = h->rows > 0 ? h->rows : h->g.ndim == 3 ? zseg_of(h) : default_rows(h);
     *flags = h->flags;
     return JACOBI_OK;
 }
@@ -1047,9 +1062,10 @@ int jacobi_autotune(jacobi_t h, int64_t n_sweeps, int with_source, int *t_depth,
             for (int rg : {2, 4, 8, 16}) cands.push_back({1, rg, JACOBI_FLAG_EXPLICIT_HALO});
         cands.push_back({1, 0, JACOBI_FLAG_EXPLICIT_HALO | JACOBI_FLAG_OVERLAP});
         if (h->g.ndim == 3) {
-            static const int kZseg[] = {8, 16, 32, 64, 128};
-            for (int z : kZseg)
-                for (int f : {0, (int)JACOBI_FLAG_NT_STORES}) cands.push_back({1, z, f});
+            static const int kZseg[] = {16, 32, 64, 128};
+            for (int d = 1; d <= jac::march3d_max_depth(); ++d)
+                for (int z : kZseg)
+                    for (int f : {0, (int)JACOBI_FLAG_NT_STORES}) cands.push_back({d, z, f});
         }
         if (h->g.ndim == 2) {
             const int *list;

@@ -87,14 +87,16 @@ hipError_t launch_march2d_batch(const BatchGrid *grids, const int *prefix, int n
 template <typename R>
 int64_t march2d_batch_work(const Geom &g, int depth, int rows);
 
-// One 3D sweep in one pass over the whole grid (k_march3d.hip), reading face
-// neighbours' cells from their owning blocks; zseg planes per work item.
-// uout may be NULL (residual only); res: one partial per work item or NULL.
+// `depth` 3D sweeps in one pass over the whole grid (k_march3d.hip), reading
+// face neighbours' cells from their owning blocks; zseg output planes per
+// work item.  uout may be NULL (residual only); res: one partial per wave
+// (4 per work item) or NULL.  depth in 1 .. march3d_max_depth().
 template <typename R>
 hipError_t launch_march3d(const Geom &g, const void *uin, void *uout, const void *b, double *res,
-                          int zseg, hipStream_t st, int64_t *nwork, int nt = 0);
+                          int zseg, hipStream_t st, int64_t *nwork, int nt = 0, int depth = 1);
 template <typename R>
-int64_t march3d_work_items(const Geom &g, int zseg);
+int64_t march3d_work_items(const Geom &g, int zseg, int depth = 1);
+int march3d_max_depth();
 
 // Batched-solver bookkeeping (k_batch.hip).
 hipError_t launch_batch_init(int count, const BatchState &st, hipStream_t s);

@@ -191,31 +191,43 @@ CASES_3D = [
     (40, 3, 5, 2, 1, 1, 4),
     (300, 20, 17, 3, 2, 2, 6),
     (1, 1, 1, 1, 1, 1, 2),
+    (130, 45, 70, 3, 3, 2, 9),   # several strips, row groups and z segments, ragged
 ]
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("case", CASES_3D)
 def test_3d_bit_exact(device, dtype, case):
+    """3D passes of every depth (1 .. the largest) and z segment, the
+    explicit-halo and overlapped orders: states bit-exact with the oracle,
+    residuals (folded into the first pass of each interval) within 1e-12."""
     nx, ny, nz, bx, by, bz, K = case
-    say("3d case=%s dtype=%s" % (case, np.dtype(dtype).name))
     U0 = RNG.uniform(0, 1, (nz + 2, ny + 2, nx + 2))
     f = RNG.uniform(-1, 1, (nz, ny, nx))
     h2 = synthetic.spacing2(max(case[:3]))
     import paper_2303_02543_amd as jb
+    code = jb.JACOBI_F32 if dtype == np.float32 else jb.JACOBI_F64
     want, _ = oracle_run(U0, f, h2, K, dtype)
-    for rows, flags in ((0, 0), (8, 0), (64, 0), (0, jb.JACOBI_FLAG_EXPLICIT_HALO),
-                        (16, jb.JACOBI_FLAG_NT_STORES),
-                        (0, jb.JACOBI_FLAG_EXPLICIT_HALO | jb.JACOBI_FLAG_OVERLAP)):
-        got, res = run_device(U0, f, h2, K, (bx, by, bz), dtype, device, rows=rows, flags=flags,
-                              check_every=3)
-        assert_bits(got, want, "3d %s rows %d flags %d" % (case, rows, flags))
-        b = oracle.scale_source(np.asarray(f, dtype=dtype), h2, dtype)
-        ores, _ = oracle_residuals(np.asarray(U0, dtype=dtype), b, K, 3)
+    b = oracle.scale_source(np.asarray(f, dtype=dtype), h2, dtype)
+    ores, _ = oracle_residuals(np.asarray(U0, dtype=dtype), b, K, 4)
+    scheds = [(d, rows, 0) for d in range(1, jb.jacobi_max_depth(3, code) + 1)
+              for rows in (0, 8, 64)]
+    scheds += [(2, 16, jb.JACOBI_FLAG_NT_STORES), (1, 0, jb.JACOBI_FLAG_EXPLICIT_HALO),
+               (1, 0, jb.JACOBI_FLAG_EXPLICIT_HALO | jb.JACOBI_FLAG_OVERLAP)]
+    for depth, rows, flags in scheds:
+        say("3d case=%s dtype=%s depth=%d rows=%d flags=%d"
+            % (case, np.dtype(dtype).name, depth, rows, flags))
+        got, _ = run_device(U0, f, h2, K, (bx, by, bz), dtype, device, depth=depth, rows=rows,
+                            flags=flags)
+        assert_bits(got, want, "3d %s depth %d rows %d flags %d" % (case, depth, rows, flags))
+        got, res = run_device(U0, f, h2, K, (bx, by, bz), dtype, device, depth=depth, rows=rows,
+                              flags=flags, check_every=4)
+        assert_bits(got, want, "3d solve %s depth %d rows %d flags %d" % (case, depth, rows, flags))
         np.testing.assert_allclose(res, ores, rtol=1e-12, atol=0)
     want_l, _ = oracle_run(U0, None, h2, K, dtype)
-    got_l, _ = run_device(U0, None, h2, K, (bx, by, bz), dtype, device)
-    assert_bits(got_l, want_l, "3d laplace %s" % (case,))
+    for depth in range(1, jb.jacobi_max_depth(3, code) + 1):
+        got_l, _ = run_device(U0, None, h2, K, (bx, by, bz), dtype, device, depth=depth)
+        assert_bits(got_l, want_l, "3d laplace %s depth %d" % (case, depth))
 
 
 # ------------------------------------------------ FP32 against the FP64 oracle
