@@ -110,6 +110,39 @@ int jacobi_workspace_bytes(int ndim, const int64_t *grid, const int64_t *blocks,
 int jacobi_create(int ndim, const int64_t *grid, const int64_t *blocks, int dtype,
                   void *workspace, size_t workspace_bytes, void *stream, jacobi_t *out);
 
+/* Implements: Section 4.3's per-iteration face exchange between cuboids and
+ * Section 4.4's over-decomposition in their communication-avoiding form
+ * (deep-halo block storage; the exchange pattern is the paper's, its depth
+ * this library's choice).  Every block stores a frame of H nodes around its
+ * interior (faces, edges and corners); each pass first refreshes every
+ * frame from the blocks owning those nodes (one exchange launch), then runs
+ * up to H sweeps of every block from that block's own storage alone (one
+ * launch over all blocks), so blocks exchange data once per H sweeps.
+ *   ndim, grid, blocks, dtype  as for jacobi_workspace_bytes
+ *   halo    requested frame depth H, 1 <= H <= 64; it is stored rounded up
+ *           to the next value with (H - 1) a multiple of 16 bytes of
+ *           elements (FP32: 1, 5, 9, 13, ...; FP64: 1, 3, 5, ...; see
+ *           jacobi_get_halo), which must not exceed the extent of any block
+ *           on an axis with more than one block (JACOBI_E_INVAL otherwise)
+ *   bytes   out: workspace size.  JACOBI_E_INVAL on overflow. */
+int jacobi_deep_workspace_bytes(int ndim, const int64_t *grid, const int64_t *blocks, int dtype,
+                                int halo, size_t *bytes);
+
+/* Implements: as jacobi_deep_workspace_bytes.  Create a handle over a
+ * caller-owned workspace of jacobi_deep_workspace_bytes bytes (256-byte
+ * aligned, device memory).  The handle supports every call a jacobi_create
+ * handle does, with identical results (bit for bit); jacobi_sweep and
+ * jacobi_solve run deep-halo passes of up to min(t_depth, stored H) sweeps
+ * (the residual, when asked for, is a pass of its own), and
+ * JACOBI_FLAG_EXPLICIT_HALO still selects the one-cell exchange before every
+ * sweep. */
+int jacobi_deep_create(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, int halo,
+                       void *workspace, size_t workspace_bytes, void *stream, jacobi_t *out);
+
+/* Not in the paper (a query).  Stored frame depth of a deep-halo handle, 0
+ * for a jacobi_create handle.  JACOBI_E_INVAL for a NULL pointer. */
+int jacobi_get_halo(jacobi_t h, int *halo);
+
 /* Library plumbing (no passage).  Wait for the handle's stream, then free
  * the host object.  NULL is a no-op.  The workspace stays the caller's. */
 int jacobi_destroy(jacobi_t h);

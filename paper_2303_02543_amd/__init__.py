@@ -49,6 +49,9 @@ _PI64 = ctypes.POINTER(ctypes.c_int64)
 _SIGNATURES = {
     "jacobi_workspace_bytes": [_I, _PI64, _PI64, _I, ctypes.POINTER(_SZ)],
     "jacobi_create": [_I, _PI64, _PI64, _I, _P, _SZ, _P, ctypes.POINTER(_P)],
+    "jacobi_deep_workspace_bytes": [_I, _PI64, _PI64, _I, _I, ctypes.POINTER(_SZ)],
+    "jacobi_deep_create": [_I, _PI64, _PI64, _I, _I, _P, _SZ, _P, ctypes.POINTER(_P)],
+    "jacobi_get_halo": [_P, ctypes.POINTER(_I)],
     "jacobi_destroy": [_P],
     "jacobi_set_stream": [_P, _P],
     "jacobi_get_layout": [_P, _PI64, _PI64],
@@ -160,6 +163,28 @@ def jacobi_create(ndim, grid, blocks, dtype, workspace_ptr, workspace_bytes, str
     _check(lib().jacobi_create(int(ndim), _arr64(grid), _arr64(blocks), int(dtype),
                                workspace_ptr, int(workspace_bytes), stream_ptr, ctypes.byref(h)))
     return h
+
+
+def jacobi_deep_workspace_bytes(ndim, grid, blocks, dtype, halo):
+    out = _SZ(0)
+    _check(lib().jacobi_deep_workspace_bytes(int(ndim), _arr64(grid), _arr64(blocks), int(dtype),
+                                             int(halo), ctypes.byref(out)))
+    return out.value
+
+
+def jacobi_deep_create(ndim, grid, blocks, dtype, halo, workspace_ptr, workspace_bytes,
+                       stream_ptr):
+    h = _P()
+    _check(lib().jacobi_deep_create(int(ndim), _arr64(grid), _arr64(blocks), int(dtype),
+                                    int(halo), workspace_ptr, int(workspace_bytes), stream_ptr,
+                                    ctypes.byref(h)))
+    return h
+
+
+def jacobi_get_halo(h):
+    v = _I()
+    _check(lib().jacobi_get_halo(h, ctypes.byref(v)))
+    return v.value
 
 
 def jacobi_destroy(h):
@@ -356,7 +381,7 @@ class Solver:
     have shape (n_y+2, n_x+2) / (n_z+2, n_y+2, n_x+2), sources (n_y, n_x) / ...
     """
 
-    def __init__(self, grid, blocks, dtype, device="cuda", stream=None):
+    def __init__(self, grid, blocks, dtype, device="cuda", stream=None, halo=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the Jacobi library has no CPU path")
@@ -366,6 +391,15 @@ class Solver:
         self.torch_dtype = dtype
         self.dtype = dtype_code(dtype)
         self.device = torch.device(device)
+        if halo:
+            # deep-halo block storage: frames of `halo` nodes, exchanged once
+            # per pass of up to that many sweeps
+            nbytes = jacobi_deep_workspace_bytes(self.ndim, self.grid, self.blocks, self.dtype,
+                                                 halo)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.h = jacobi_deep_create(self.ndim, self.grid, self.blocks, self.dtype, halo,
+                                        _ptr(self.workspace), nbytes, _stream_handle(stream))
+            return
         nbytes = jacobi_workspace_bytes(self.ndim, self.grid, self.blocks, self.dtype)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.h = jacobi_create(self.ndim, self.grid, self.blocks, self.dtype,
@@ -506,6 +540,10 @@ class Solver:
 
     def layout(self):
         return jacobi_get_layout(self.h)
+
+    def halo(self):
+        """Stored frame depth of a deep-halo solver (0 for a standard one)."""
+        return jacobi_get_halo(self.h)
 
     def close(self):
         # the library frees the handle even when it reports an error, so

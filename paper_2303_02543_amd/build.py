@@ -19,7 +19,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
 SOURCES = ["jacobi_abi.hip", "k_layout.hip", "k_sweep.hip", "k_march2d.hip", "k_march3d.hip",
-           "k_residual.hip", "k_batch.hip"]
+           "k_residual.hip", "k_batch.hip", "k_deep.hip"]
 # k_march2d.hip is compiled once per temporal depth (its kernels) and once
 # more for the depth dispatch; each entry: (source, object name, defines)
 MARCH2D_DEPTHS = list(range(1, 9)) + [10, 11, 12, 13, 14, 16]

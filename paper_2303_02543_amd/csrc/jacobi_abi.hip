@@ -159,6 +159,133 @@ int plan(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, Geom *
     return JACOBI_OK;
 }
 
+constexpr int kDeepMaxDepth = 16;  // prefix tables per pass depth 1 .. 16
+
+// Deep-halo layout on top of plan(): every block stores local nodes -Hs ..
+// e+Hs-1 on each axis (Hs = the requested halo rounded up so that a small
+// grid's first interior column is 16-byte aligned whether or not it extends
+// into a neighbour), in rows of pitch_d elements whose column Hs-1 past
+// 128 bytes holds local x = 0.  g is rewritten to a view of that storage
+// (pitch, plane, bstride and ax), so local_offset addresses it; the blocked
+// source keeps plan()'s layout.  Workspace: two state buffers, the blocked
+// source, the deep source, residual partials, scratch, two descriptor tables,
+// prefix tables, activity flags and a pass counter.
+struct DeepLayout {
+    int hs;
+    size_t off_bd, off_tab, off_prefix, off_active, off_pc;
+};
+
+int plan_deep(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, int halo, Geom *g,
+              Layout *l, DeepLayout *dl) {
+    int rc = plan(ndim, grid, blocks, dtype, g, l);
+    if (rc != JACOBI_OK) return rc;
+    if (halo < 1 || halo > 64) return fail(JACOBI_E_INVAL, "halo must be in [1, 64] (got %d)", halo);
+    const size_t es = dtype == JACOBI_F32 ? 4 : 8;
+    const int V = (int)(16 / es);
+    const int hs = 1 + (halo - 1 + V - 1) / V * V;
+    // a small grid reaching into a neighbour must stay inside the domain
+    for (int a = 0; a < ndim; ++a) {
+        if (g->nb[a] < 2) continue;
+        const int last = g->n[a] - (g->nb[a] - 1) * g->e[a];
+        const int lim = last < g->e[a] ? last : g->e[a];
+        if (hs > lim)
+            return fail(JACOBI_E_INVAL,
+                        "halo %d (stored %d) exceeds the block extent %d on axis %d", halo, hs, lim,
+                        a);
+    }
+    const size_t axc = 128 / es;
+    const size_t co = axc + hs - 1;  // storage column of local x = 0
+    const size_t pitch = round_up(co + (size_t)g->e[0] + hs + V, axc);
+    const size_t rows = (size_t)g->e[1] + 2 * hs;
+    const size_t plane = rows * pitch;
+    size_t bstride = ndim == 3 ? plane * ((size_t)g->e[2] + 2 * hs) : plane;
+    bstride = round_up(bstride + axc, 64);
+    size_t ax = co + (size_t)(hs - 1) * pitch + (ndim == 3 ? (size_t)(hs - 1) * plane : 0);
+    if (ax > ((size_t)1 << 30)) return fail(JACOBI_E_INVAL, "size overflow");
+    g->pitch = (int64_t)pitch;
+    g->plane = (int64_t)plane;
+    g->bstride = (int64_t)bstride;
+    g->ax = (int)ax;
+    size_t sbytes, t;
+    if (!mul_ok((size_t)g->nblocks, bstride, &sbytes) || !mul_ok(sbytes, es, &sbytes) ||
+        sbytes > ((size_t)1 << 62))
+        return fail(JACOBI_E_INVAL, "size overflow");
+    const size_t bbytes = l->off_part - l->off_b;  // the blocked source (plan's layout)
+    const size_t part_bytes = l->off_scratch - l->off_part;
+    size_t off = 0;
+    l->off_u0 = off;
+    off = round_up(off + sbytes, kAlign);
+    l->off_u1 = off;
+    off = round_up(off + sbytes, kAlign);
+    l->off_b = off;
+    off = round_up(off + bbytes, kAlign);
+    dl->off_bd = off;
+    off = round_up(off + sbytes, kAlign);
+    l->off_part = off;
+    off = round_up(off + part_bytes, kAlign);
+    l->off_scratch = off;
+    off = round_up(off + kAlign, kAlign);
+    const size_t nb = (size_t)g->nblocks;
+    dl->off_tab = off;
+    off = round_up(off + 2 * nb * sizeof(jac::BatchGrid), kAlign);
+    dl->off_prefix = off;
+    off = round_up(off + (kDeepMaxDepth + 1) * (nb + 1) * sizeof(int), kAlign);
+    dl->off_active = off;
+    off = round_up(off + nb * sizeof(int), kAlign);
+    dl->off_pc = off;
+    if (!add_ok(off, kAlign, &t)) return fail(JACOBI_E_INVAL, "size overflow");
+    l->bytes = t;
+    dl->hs = hs;
+    return JACOBI_OK;
+}
+
+// The small grid of block blk in the deep layout: the block's interior
+// extended by hs-1 nodes into every neighbour, with its ring on the layer
+// beyond (a neighbour's nodes, refreshed by the exchange before each pass)
+// or on the domain's Dirichlet ring.  Geometry of one unblocked grid whose
+// state rows / planes are those of the deep storage and whose source rows
+// are those of the deep source; u[k] from buffer bufk, b from bd.
+jac::BatchGrid small_grid(const Geom &g, int hs, int64_t blk, int dtype, char *buf0, char *buf1,
+                          char *bd) {
+    const size_t es = dtype == JACOBI_F32 ? 4 : 8;
+    const int bi[3] = {(int)(blk % g.nb[0]), (int)((blk / g.nb[0]) % g.nb[1]),
+                       g.ndim == 3 ? (int)(blk / ((int64_t)g.nb[0] * g.nb[1])) : 0};
+    int lo[3] = {0, 0, 0}, n[3] = {1, 1, 1};
+    for (int a = 0; a < g.ndim; ++a) {
+        const int ext = jac::extent(g.n[a], g.e[a], bi[a]);
+        lo[a] = bi[a] > 0 ? -(hs - 1) : 0;
+        const int hi = bi[a] < g.nb[a] - 1 ? ext + hs - 1 : ext;
+        n[a] = hi - lo[a];
+    }
+    jac::BatchGrid d;
+    std::memset(&d, 0, sizeof d);
+    Geom &s = d.g;
+    s.ndim = g.ndim;
+    const int64_t co = (int64_t)(128 / es) + hs - 1;
+    s.ax = (int)(co + lo[0]);
+    for (int a = 0; a < 3; ++a) {
+        s.n[a] = n[a];
+        s.nb[a] = 1;
+    }
+    // e: source row stride (the deep pitch), rows per source plane, and a
+    // z extent no plane reaches (one block per axis)
+    s.e[0] = (int)g.pitch;
+    s.e[1] = g.ndim == 3 ? (int)(g.plane / g.pitch) : (1 << 30);
+    s.e[2] = 1 << 30;
+    s.pitch = g.pitch;
+    s.plane = g.plane;
+    s.bstride = g.bstride;
+    s.sstride = 0;
+    s.nblocks = 1;
+    const int64_t zpart = g.ndim == 3 ? (int64_t)(lo[2] + hs - 1) * g.plane : 0;
+    const int64_t ring = blk * g.bstride + zpart + (int64_t)(lo[1] + hs - 1) * g.pitch;
+    d.u[0] = buf0 + ring * es;
+    d.u[1] = buf1 + ring * es;
+    const int64_t bz = g.ndim == 3 ? (int64_t)(lo[2] + hs) * g.plane : 0;
+    d.b = bd + (blk * g.bstride + bz + (int64_t)(lo[1] + hs) * g.pitch + co + lo[0]) * es;
+    return d;
+}
+
 }  // namespace
 
 // Device scratch of jacobi_solve_noalloc: a file-scope array of fixed size,
@@ -199,6 +326,18 @@ struct jacobi_s {
     hipStream_t stream2 = nullptr;
     hipEvent_t ev_piece[kPieces] = {};
     hipEvent_t ev_join = nullptr;
+    // deep-halo block storage (halo > 0): the state buffers hold an H-deep
+    // frame around every block; bdeep is the source in the same layout, and
+    // each pass runs every block as its own small grid from a descriptor
+    // table (one per buffer parity) and work-prefix tables per depth
+    int halo = 0;
+    void *bdeep = nullptr;
+    jac::BatchGrid *d_tab[2] = {nullptr, nullptr};
+    int *d_prefix = nullptr;
+    int *d_active = nullptr;
+    int *d_pc = nullptr;
+    int tab_rows = 0;  // tile height / z segment the prefix tables hold (0: none)
+    std::vector<int> h_prefix;
 };
 
 namespace {
@@ -409,10 +548,14 @@ int do_sweep_overlap(jacobi_t h, int64_t n, double *res_first) {
 // sync_halos is set; the explicit-halo sweep keeps them valid after every
 // sweep, as it must.
 template <typename R>
+int do_deep_sweep(jacobi_t h, int64_t n, double *res_first, bool sync_halos);
+
+template <typename R>
 int do_sweep(jacobi_t h, int64_t n, double *res_first, bool sync_halos = true) {
     const void *b = h->has_source ? h->b : nullptr;
     const bool explicit_halo = (h->flags & JACOBI_FLAG_EXPLICIT_HALO) != 0 ||
                                (h->g.ndim == 2 && !march_fits(h->g, h->dtype));
+    if (h->halo > 0 && !explicit_halo) return do_deep_sweep<R>(h, n, res_first, sync_halos);
     if (h->g.ndim == 3 && !explicit_halo && n > 0) {
         // fused 3D passes of up to `depth` sweeps each, split as evenly as
         // possible; the first also sums the residual of its input
@@ -530,6 +673,138 @@ int do_sweep(jacobi_t h, int64_t n, double *res_first, bool sync_halos = true) {
     return JACOBI_OK;
 }
 
+// Deep-halo passes ------------------------------------------------------
+
+// Descriptor and work-prefix tables of the small grids for tile height (2D)
+// or z segment (3D) `rows`; uploaded when it changes.
+template <typename R>
+int deep_tables(jacobi_t h, int rows) {
+    if (h->tab_rows == rows) return JACOBI_OK;
+    const int64_t nb = h->g.nblocks;
+    std::vector<jac::BatchGrid> t[2];
+    for (int p = 0; p < 2; ++p) {
+        t[p].resize(nb);
+        for (int64_t k = 0; k < nb; ++k)
+            t[p][k] = small_grid(h->g, h->halo, k, h->dtype, (char *)h->u[p], (char *)h->u[p ^ 1],
+                                 (char *)h->bdeep);
+    }
+    h->h_prefix.assign((size_t)(kDeepMaxDepth + 1) * (nb + 1), -1);
+    for (int d = 1; d <= kDeepMaxDepth; ++d) {
+        int *pre = &h->h_prefix[(size_t)d * (nb + 1)];
+        int64_t acc = 0;
+        for (int64_t k = 0; k < nb && acc >= 0; ++k) {
+            pre[k] = (int)acc;
+            const int64_t w = h->g.ndim == 2 ? jac::march2d_batch_work<R>(t[0][k].g, d, rows)
+                                             : jac::march3d_batch_items<R>(t[0][k].g, rows, d);
+            if (w < 0) {
+                acc = -1;
+                break;
+            }
+            acc += w;
+            if (acc > 0x3fffffff) return fail(JACOBI_E_INVAL, "deep-halo pass exceeds 2^30 work items");
+        }
+        pre[nb] = (int)acc;
+    }
+    std::vector<int> ones((size_t)nb, 1);
+    const int zero = 0;
+    for (int p = 0; p < 2; ++p)
+        HIP_TRY(hipMemcpyAsync(h->d_tab[p], t[p].data(), sizeof(jac::BatchGrid) * nb,
+                               hipMemcpyHostToDevice, h->stream),
+                "deep table upload");
+    HIP_TRY(hipMemcpyAsync(h->d_prefix, h->h_prefix.data(), sizeof(int) * h->h_prefix.size(),
+                           hipMemcpyHostToDevice, h->stream),
+            "deep table upload");
+    HIP_TRY(hipMemcpyAsync(h->d_active, ones.data(), sizeof(int) * nb, hipMemcpyHostToDevice,
+                           h->stream),
+            "deep table upload");
+    HIP_TRY(hipMemcpyAsync(h->d_pc, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream),
+            "deep table upload");
+    HIP_TRY(hipStreamSynchronize(h->stream), "stream synchronize");
+    h->tab_rows = rows;
+    return JACOBI_OK;
+}
+
+// Tile height of the 2D small-grid passes at `depth`: the smallest whose
+// work items over all blocks fit one round of resident waves.
+template <typename R>
+int deep_rows(jacobi_t h, int depth) {
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 64;
+    const int wpc = jac::march2d_waves_per_cu<R>(depth, h->has_source ? 1 : 0, 0);
+    if (wpc <= 0) return 64;
+    const int64_t slots = (int64_t)wpc * cus;
+    std::vector<jac::BatchGrid> t((size_t)h->g.nblocks);
+    int maxn = kMinRows;
+    for (int64_t k = 0; k < h->g.nblocks; ++k) {
+        t[k] = small_grid(h->g, h->halo, k, h->dtype, nullptr, nullptr, nullptr);
+        if (t[k].g.n[1] > maxn) maxn = t[k].g.n[1];
+    }
+    auto work = [&](int rows) {
+        int64_t acc = 0;
+        for (const auto &d : t) acc += jac::march2d_batch_work<R>(d.g, depth, rows);
+        return acc;
+    };
+    int lo = kMinRows, hi = maxn;
+    if (work(hi) > slots) return hi;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo) / 2;
+        if (work(mid) <= slots) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// n sweeps of a deep-halo handle: passes of up to min(depth, halo) sweeps,
+// each an H-deep frame exchange followed by one launch over every block's
+// small grid (each reads only its own block's storage).
+template <typename R>
+int do_deep_sweep(jacobi_t h, int64_t n, double *res_first, bool sync_halos) {
+    if (res_first) {
+        int rc = do_residual<R>(h, res_first);
+        if (rc) return rc;
+    }
+    if (n == 0) return JACOBI_OK;
+    const int nd = h->g.ndim;
+    int depth = h->depth > 0 ? h->depth : default_depth(h);
+    if (depth > h->halo) depth = h->halo;
+    if (nd == 2) depth = pick_depth(h->dtype, depth);
+    const int rows = nd == 2 ? (h->rows > 0 ? h->rows : deep_rows<R>(h, depth)) : zseg_of(h);
+    int rc = deep_tables<R>(h, rows);
+    if (rc) return rc;
+    const int64_t nb = h->g.nblocks;
+    int64_t left = n;
+    while (left > 0) {
+        const int64_t passes = (left + depth - 1) / depth;
+        int t = (int)((left + passes - 1) / passes);
+        if (nd == 2) t = pick_depth(h->dtype, t);
+        const int nwork = h->h_prefix[(size_t)t * (nb + 1) + nb];
+        if (nwork < 0) return fail(JACOBI_E_INVAL, "no deep-halo pass of depth %d", t);
+        HIP_TRY(jac::launch_deep_exchange<R>(h->g, h->u[h->cur], h->halo, h->stream),
+                "deep exchange launch");
+        rc = prof_begin(h);
+        if (rc) return rc;
+        const int *pre = h->d_prefix + (size_t)t * (nb + 1);
+        if (nd == 2)
+            HIP_TRY(jac::launch_march2d_batch<R>(h->d_tab[h->cur], pre, (int)nb, h->d_active, h->d_pc,
+                                                 nullptr, true, t, rows, nwork, h->stream, 0,
+                                                 h->has_source ? 1 : 0),
+                    "deep pass launch");
+        else
+            HIP_TRY(jac::launch_march3d_batch<R>(h->d_tab[h->cur], pre, (int)nb, h->has_source, t,
+                                                 rows, nwork, h->stream),
+                    "deep pass launch");
+        rc = prof_end(h, t);
+        if (rc) return rc;
+        h->cur ^= 1;
+        left -= t;
+    }
+    if (sync_halos)
+        HIP_TRY(jac::launch_halo_exchange<R>(h->g, h->u[h->cur], h->stream), "halo exchange launch");
+    return JACOBI_OK;
+}
+
 // Adjoint passes: n sweeps of the zero-ring state with the FP64 accumulation.
 template <typename R>
 int do_adjoint(jacobi_t h, int64_t n) {
@@ -644,6 +919,60 @@ int jacobi_create(int ndim, const int64_t *grid, const int64_t *blocks, int dtyp
     return JACOBI_OK;
 }
 
+int jacobi_deep_workspace_bytes(int ndim, const int64_t *grid, const int64_t *blocks, int dtype,
+                                int halo, size_t *bytes) {
+    if (!bytes) return fail(JACOBI_E_INVAL, "bytes must not be NULL");
+    Geom g;
+    Layout l;
+    DeepLayout dl;
+    const int rc = plan_deep(ndim, grid, blocks, dtype, halo, &g, &l, &dl);
+    if (rc != JACOBI_OK) return rc;
+    *bytes = l.bytes;
+    return JACOBI_OK;
+}
+
+int jacobi_deep_create(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, int halo,
+                       void *workspace, size_t workspace_bytes, void *stream, jacobi_t *out) {
+    if (!out) return fail(JACOBI_E_INVAL, "out must not be NULL");
+    *out = nullptr;
+    Geom g;
+    Layout l;
+    DeepLayout dl;
+    int rc = plan_deep(ndim, grid, blocks, dtype, halo, &g, &l, &dl);
+    if (rc != JACOBI_OK) return rc;
+    if (!workspace) return fail(JACOBI_E_INVAL, "workspace must not be NULL");
+    if ((uintptr_t)workspace % kAlign)
+        return fail(JACOBI_E_INVAL, "workspace must be %zu-byte aligned", kAlign);
+    if (workspace_bytes < l.bytes)
+        return fail(JACOBI_E_NOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, l.bytes);
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, workspace);
+    if (e != hipSuccess) return hip_fail(e, "workspace pointer query");
+    if (attr.type != hipMemoryTypeDevice)
+        return fail(JACOBI_E_INVAL, "workspace is not device memory");
+    jacobi_s *h = new (std::nothrow) jacobi_s();
+    if (!h) return fail(JACOBI_E_NOMEM, "host allocation failed");
+    init_handle(h, g, l, dtype, workspace, stream);
+    char *ws = (char *)workspace;
+    h->halo = dl.hs;
+    h->bdeep = ws + dl.off_bd;
+    h->d_tab[0] = (jac::BatchGrid *)(ws + dl.off_tab);
+    h->d_tab[1] = h->d_tab[0] + g.nblocks;
+    h->d_prefix = (int *)(ws + dl.off_prefix);
+    h->d_active = (int *)(ws + dl.off_active);
+    h->d_pc = (int *)(ws + dl.off_pc);
+    *out = h;
+    return JACOBI_OK;
+}
+
+int jacobi_get_halo(jacobi_t h, int *halo) {
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!halo) return fail(JACOBI_E_INVAL, "halo must not be NULL");
+    *halo = h->halo;
+    return JACOBI_OK;
+}
+
 int jacobi_destroy(jacobi_t h) {
     if (!h) return JACOBI_OK;
     hipError_t e = hipStreamSynchronize(h->stream);
@@ -692,6 +1021,14 @@ int jacobi_set_state(jacobi_t h, const void *u) {
         HIP_TRY(jac::launch_halo_exchange<double>(h->g, h->u[0], h->stream), "halo exchange launch");
         HIP_TRY(jac::launch_halo_exchange<double>(h->g, h->u[1], h->stream), "halo exchange launch");
     }
+    if (h->halo > 0) {
+        // every block's whole frame, ring nodes beyond its own ring included
+        for (int k = 0; k < 2; ++k)
+            HIP_TRY(h->dtype == JACOBI_F32
+                        ? jac::launch_deep_exchange<float>(h->g, h->u[k], h->halo, h->stream)
+                        : jac::launch_deep_exchange<double>(h->g, h->u[k], h->halo, h->stream),
+                    "deep exchange launch");
+    }
     h->cur = 0;
     h->has_state = true;
     return JACOBI_OK;
@@ -722,6 +1059,11 @@ int jacobi_set_source(jacobi_t h, const void *f, double h2) {
         HIP_TRY(jac::launch_scale_source<float>(h->g, f, h->b, h2, h->stream), "source launch");
     else
         HIP_TRY(jac::launch_scale_source<double>(h->g, f, h->b, h2, h->stream), "source launch");
+    if (h->halo > 0)
+        HIP_TRY(h->dtype == JACOBI_F32
+                    ? jac::launch_deep_source<float>(h->g, h->b, h->bdeep, h->halo, h->stream)
+                    : jac::launch_deep_source<double>(h->g, h->b, h->bdeep, h->halo, h->stream),
+                "deep source launch");
     h->has_source = true;
     return JACOBI_OK;
 }

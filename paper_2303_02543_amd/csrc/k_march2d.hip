@@ -530,7 +530,9 @@ __global__ __launch_bounds__(256) void k_march2d(Geom g, const R *__restrict__ u
 // item w belongs to grid gi with prefix[gi] <= w < prefix[gi+1]; inactive
 // grids (stopped by the convergence test) skip their items.  All active
 // grids advance together, so the input buffer is u[pass_count & 1].
-template <typename R, int T, int P, bool RES>
+// MODE: Poisson (the batched solver; the deep-halo form with a source) or
+// Laplace (the deep-halo form without one).
+template <typename R, int T, int P, bool RES, int MODE>
 __global__ __launch_bounds__(256) void k_march2d_batch(const BatchGrid *__restrict__ grids,
                                                        const int *__restrict__ prefix, int ngrids,
                                                        const int *__restrict__ active,
@@ -538,7 +540,8 @@ __global__ __launch_bounds__(256) void k_march2d_batch(const BatchGrid *__restri
                                                        double *__restrict__ res, int store,
                                                        int rows, int nwork) {
     using S = M2<R, T, P>;
-    __shared__ Chunk<R, S::V> bsm[4 * S::RB * 64];
+    constexpr bool SRC = MODE == MODE_POISSON;
+    __shared__ Chunk<R, S::V> bsm[SRC ? 4 * S::RB * 64 : 1];
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int wid = __builtin_amdgcn_readfirstlane(lb * (blockDim.x >> 6) + (threadIdx.x >> 6));
     if (wid >= nwork) return;
@@ -553,10 +556,9 @@ __global__ __launch_bounds__(256) void k_march2d_batch(const BatchGrid *__restri
     const int par = *pass_count & 1;
     const R *uin = (const R *)grids[gi].u[par];
     R *uout = store ? (R *)grids[gi].u[par ^ 1] : nullptr;
-    m2_run<R, T, P, MODE_POISSON, RES>(g, uin, uout, (const R *)grids[gi].b,
-                                    RES ? res + wid : nullptr, nullptr, wid - prefix[gi], rows,
-                                    &bsm[(threadIdx.x >> 6) * S::RB * 64],
-                                    false);
+    m2_run<R, T, P, MODE, RES>(g, uin, uout, SRC ? (const R *)grids[gi].b : nullptr,
+                               RES ? res + wid : nullptr, nullptr, wid - prefix[gi], rows,
+                               &bsm[SRC ? (threadIdx.x >> 6) * S::RB * 64 : 0], false);
 }
 
 // ---- host side -------------------------------------------------------------
@@ -579,7 +581,7 @@ hipError_t m2_launch_t(const Geom &g, const void *uin, void *uout, const void *b
 template <typename R, int T>
 hipError_t m2b_launch_t(const BatchGrid *grids, const int *prefix, int ngrids, const int *active,
                         const int *pass_count, double *res, bool store, int rows, int nwork,
-                        hipStream_t st, int deep);
+                        hipStream_t st, int deep, int mode);
 template <typename R, int T>
 int m2_waves_per_cu_t(int mode, int deep);
 
@@ -636,26 +638,34 @@ hipError_t m2_launch_t(const Geom &g, const void *uin, void *uout, const void *b
 template <typename R, int T, int P>
 static hipError_t m2b_launch_p(const BatchGrid *grids, const int *prefix, int ngrids,
                                const int *active, const int *pass_count, double *res, bool store,
-                               int rows, int nwork, hipStream_t st) {
+                               int rows, int nwork, hipStream_t st, int mode) {
     const int grid = (nwork + 3) / 4;
-    if (res)
-        hipLaunchKernelGGL((k_march2d_batch<R, T, P, true>), dim3(grid), dim3(256), 0, st, grids,
-                           prefix, ngrids, active, pass_count, res, store ? 1 : 0, rows, nwork);
+    if (mode == MODE_LAPLACE) {
+        // the deep-halo form without a source: no residual, one-row prefetch
+        if (res || P != 1) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_march2d_batch<R, T, P, false, MODE_LAPLACE>), dim3(grid), dim3(256),
+                           0, st, grids, prefix, ngrids, active, pass_count, res, store ? 1 : 0,
+                           rows, nwork);
+    } else if (res)
+        hipLaunchKernelGGL((k_march2d_batch<R, T, P, true, MODE_POISSON>), dim3(grid), dim3(256),
+                           0, st, grids, prefix, ngrids, active, pass_count, res, store ? 1 : 0,
+                           rows, nwork);
     else
-        hipLaunchKernelGGL((k_march2d_batch<R, T, P, false>), dim3(grid), dim3(256), 0, st, grids,
-                           prefix, ngrids, active, pass_count, res, store ? 1 : 0, rows, nwork);
+        hipLaunchKernelGGL((k_march2d_batch<R, T, P, false, MODE_POISSON>), dim3(grid), dim3(256),
+                           0, st, grids, prefix, ngrids, active, pass_count, res, store ? 1 : 0,
+                           rows, nwork);
     return hipGetLastError();
 }
 
 template <typename R, int T>
 hipError_t m2b_launch_t(const BatchGrid *grids, const int *prefix, int ngrids, const int *active,
                         const int *pass_count, double *res, bool store, int rows, int nwork,
-                        hipStream_t st, int deep) {
+                        hipStream_t st, int deep, int mode) {
     if (deep)
         return m2b_launch_p<R, T, 3>(grids, prefix, ngrids, active, pass_count, res, store, rows,
-                                     nwork, st);
+                                     nwork, st, mode);
     return m2b_launch_p<R, T, 1>(grids, prefix, ngrids, active, pass_count, res, store, rows,
-                                 nwork, st);
+                                 nwork, st, mode);
 }
 
 template <typename R, int T>
@@ -684,7 +694,7 @@ int m2_waves_per_cu_t(int mode, int deep) {
                                           int, int);                                           \
     template hipError_t m2b_launch_t<R, T>(const BatchGrid *, const int *, int, const int *,   \
                                            const int *, double *, bool, int, int,              \
-                                           hipStream_t, int);                                  \
+                                           hipStream_t, int, int);                             \
     template int m2_waves_per_cu_t<R, T>(int, int);
 
 JAC_M2_INSTANTIATE(float, JAC_MARCH2D_DEPTH)
@@ -761,10 +771,11 @@ int64_t march2d_batch_work(const Geom &g, int depth, int rows) {
 template <typename R>
 hipError_t launch_march2d_batch(const BatchGrid *grids, const int *prefix, int ngrids,
                                 const int *active, const int *pass_count, double *res, bool store,
-                                int depth, int rows, int nwork, hipStream_t st, int deep) {
+                                int depth, int rows, int nwork, hipStream_t st, int deep,
+                                int mode) {
     if (nwork <= 0) return hipSuccess;
     JAC_M2_SWITCH(depth, m2b_launch_t, R, hipErrorInvalidValue, grids, prefix, ngrids, active,
-                  pass_count, res, store, rows, nwork, st, deep)
+                  pass_count, res, store, rows, nwork, st, deep, mode)
 }
 
 template hipError_t launch_sweep2d_march<float>(const Geom &, const void *, void *, const void *,
@@ -777,10 +788,10 @@ template int64_t march2d_batch_work<float>(const Geom &, int, int);
 template int64_t march2d_batch_work<double>(const Geom &, int, int);
 template hipError_t launch_march2d_batch<float>(const BatchGrid *, const int *, int, const int *,
                                                 const int *, double *, bool, int, int, int,
-                                                hipStream_t, int);
+                                                hipStream_t, int, int);
 template hipError_t launch_march2d_batch<double>(const BatchGrid *, const int *, int, const int *,
                                                  const int *, double *, bool, int, int, int,
-                                                 hipStream_t, int);
+                                                 hipStream_t, int, int);
 template int64_t march2d_work_items<float>(const Geom &, int, int);
 template int64_t march2d_work_items<double>(const Geom &, int, int);
 template int march2d_waves_per_cu<float>(int, int, int);

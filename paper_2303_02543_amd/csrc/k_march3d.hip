@@ -315,22 +315,18 @@ __device__ __forceinline__ void m3_body(const Geom &g, const R *__restrict__ uin
     }
 }
 
-// Work item (one workgroup of 4 waves): 16 rows (fastest), column strip, z
-// segment of `zseg` output planes; wave q takes rows y0+4q .. y0+4q+3.  The
-// residual partials are per wave: work item i owns partials 4i .. 4i+3.
+// Work item (one workgroup of 4 waves) number `item` of a grid cut into
+// ngrp row groups (fastest), nstrips column strips and z segments of `zseg`
+// output planes; wave q takes rows y0+4q .. y0+4q+3.  The residual partials
+// are per wave: work item i owns partials 4i .. 4i+3 (res points at them).
 template <typename R, int T, int MODE, bool RES>
-__global__ __launch_bounds__(256) void k_march3d(Geom g, const R *__restrict__ uin,
-                                                 R *__restrict__ uout,
-                                                 const R *__restrict__ bsrc,
-                                                 double *__restrict__ res, int nstrips, int ngrp,
-                                                 int zseg, int nitems, int nt) {
+__device__ __forceinline__ void m3_item(const Geom &g, const R *__restrict__ uin,
+                                        R *__restrict__ uout, const R *__restrict__ bsrc,
+                                        double *__restrict__ res, int item, int nstrips, int ngrp,
+                                        int zseg, int nt, M3Sh<R, T> sh) {
     using M = M3<R, T>;
     constexpr int V = M::V;
     constexpr int W = M::W;
-    // per level 0 .. T-1: two plane buffers of rows y0-1 .. y0+16
-    __shared__ Chunk<R, V> sh[T][2][kM3Rows + 2][16];
-    const int item = xcd_logical_block(blockIdx.x, gridDim.x);
-    if (item >= nitems) return;  // whole workgroup
     const int grp = item % ngrp;
     const int rest = item / ngrp;
     const int strip = rest % nstrips;
@@ -386,6 +382,45 @@ __global__ __launch_bounds__(256) void k_march3d(Geom g, const R *__restrict__ u
         m3_body<R, T, MODE, false, RES>(g, uin, uout, bsrc, slot, L, oz0, oz1, ntb, sh);
 }
 
+template <typename R, int T, int MODE, bool RES>
+__global__ __launch_bounds__(256) void k_march3d(Geom g, const R *__restrict__ uin,
+                                                 R *__restrict__ uout,
+                                                 const R *__restrict__ bsrc,
+                                                 double *__restrict__ res, int nstrips, int ngrp,
+                                                 int zseg, int nitems, int nt) {
+    // per level 0 .. T-1: two plane buffers of rows y0-1 .. y0+16
+    __shared__ Chunk<R, M3<R, T>::V> sh[T][2][kM3Rows + 2][16];
+    const int item = xcd_logical_block(blockIdx.x, gridDim.x);
+    if (item >= nitems) return;  // whole workgroup
+    m3_item<R, T, MODE, RES>(g, uin, uout, bsrc, res, item, nstrips, ngrp, zseg, nt, sh);
+}
+
+// Batched pass: the work items of many grids in one launch (one descriptor
+// each; the deep-halo form runs every block as its own grid).  Work item w
+// belongs to grid gi with prefix[gi] <= w < prefix[gi+1]; every grid's input
+// is u[0] and its output u[1].
+template <typename R, int T, int MODE>
+__global__ __launch_bounds__(256) void k_march3d_batch(const BatchGrid *__restrict__ grids,
+                                                       const int *__restrict__ prefix,
+                                                       int ngrids, int zseg, int nitems) {
+    using M = M3<R, T>;
+    __shared__ Chunk<R, M::V> sh[T][2][kM3Rows + 2][16];
+    const int w = xcd_logical_block(blockIdx.x, gridDim.x);
+    if (w >= nitems) return;  // whole workgroup
+    int lo = 0, hi = ngrids;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= w) lo = mid; else hi = mid;
+    }
+    const int gi = lo;
+    const Geom g = grids[gi].g;
+    const int nstrips = (g.n[0] + M::OW - 1) / M::OW;
+    const int ngrp = (g.n[1] + M::OY - 1) / M::OY;
+    m3_item<R, T, MODE, false>(g, (const R *)grids[gi].u[0], (R *)grids[gi].u[1],
+                               (const R *)grids[gi].b, nullptr, w - prefix[gi], nstrips, ngrp, zseg,
+                               0, sh);
+}
+
 template <typename R, int T>
 static void m3_shape(const Geom &g, int zseg, int &nstrips, int &ngrp, int &nzs) {
     using M = M3<R, T>;
@@ -426,7 +461,38 @@ static hipError_t m3_launch(const Geom &g, const void *uin, void *uout, const vo
     return hipGetLastError();
 }
 
+template <typename R, int T>
+static hipError_t m3b_launch(const BatchGrid *grids, const int *prefix, int ngrids, bool src,
+                             int zseg, int nitems, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    if (src)
+        hipLaunchKernelGGL((k_march3d_batch<R, T, 1>), dim3(nitems), dim3(256), 0, st, grids,
+                           prefix, ngrids, zseg, nitems);
+    else
+        hipLaunchKernelGGL((k_march3d_batch<R, T, 0>), dim3(nitems), dim3(256), 0, st, grids,
+                           prefix, ngrids, zseg, nitems);
+    return hipGetLastError();
+}
+
 int march3d_max_depth() { return 4; }
+
+template <typename R>
+int64_t march3d_batch_items(const Geom &g, int zseg, int depth) {
+    const int64_t w = march3d_work_items<R>(g, zseg, depth);
+    return w < 0 ? w : w / 4;
+}
+
+template <typename R>
+hipError_t launch_march3d_batch(const BatchGrid *grids, const int *prefix, int ngrids, bool src,
+                                int depth, int zseg, int nitems, hipStream_t st) {
+    switch (depth) {
+    case 1: return m3b_launch<R, 1>(grids, prefix, ngrids, src, zseg, nitems, st);
+    case 2: return m3b_launch<R, 2>(grids, prefix, ngrids, src, zseg, nitems, st);
+    case 3: return m3b_launch<R, 3>(grids, prefix, ngrids, src, zseg, nitems, st);
+    case 4: return m3b_launch<R, 4>(grids, prefix, ngrids, src, zseg, nitems, st);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 // Residual partials of one pass (one per wave, 4 per work item).
 template <typename R>
@@ -452,6 +518,12 @@ hipError_t launch_march3d(const Geom &g, const void *uin, void *uout, const void
     }
 }
 
+template int64_t march3d_batch_items<float>(const Geom &, int, int);
+template int64_t march3d_batch_items<double>(const Geom &, int, int);
+template hipError_t launch_march3d_batch<float>(const BatchGrid *, const int *, int, bool, int, int,
+                                                int, hipStream_t);
+template hipError_t launch_march3d_batch<double>(const BatchGrid *, const int *, int, bool, int,
+                                                 int, int, hipStream_t);
 template int64_t march3d_work_items<float>(const Geom &, int, int);
 template int64_t march3d_work_items<double>(const Geom &, int, int);
 template hipError_t launch_march3d<float>(const Geom &, const void *, void *, const void *,

@@ -79,10 +79,12 @@ int march2d_depths(int dtype, const int **list);
 // Batched pass over the grids of a batch (Poisson kernels; see
 // k_march2d_batch).  nwork = prefix[ngrids]; res: one partial per work item
 // (NULL: no residual); store = false: residual only.
+// mode: 1 Poisson (the grids' sources), 0 Laplace (no residual, deep = 0).
 template <typename R>
 hipError_t launch_march2d_batch(const BatchGrid *grids, const int *prefix, int ngrids,
                                 const int *active, const int *pass_count, double *res, bool store,
-                                int depth, int rows, int nwork, hipStream_t st, int deep = 0);
+                                int depth, int rows, int nwork, hipStream_t st, int deep = 0,
+                                int mode = 1);
 // Work items of one grid at this depth / tile height.
 template <typename R>
 int64_t march2d_batch_work(const Geom &g, int depth, int rows);
@@ -97,6 +99,25 @@ hipError_t launch_march3d(const Geom &g, const void *uin, void *uout, const void
 template <typename R>
 int64_t march3d_work_items(const Geom &g, int zseg, int depth = 1);
 int march3d_max_depth();
+
+// Batched 3D pass (k_march3d.hip): the work items of every grid of a
+// descriptor table in one launch, each grid read from u[0] and written to
+// u[1]; src: Poisson (the grids' sources) or Laplace.  prefix[i]: first work
+// item of grid i, prefix[ngrids] = nitems.  march3d_batch_items: work items
+// of one grid.
+template <typename R>
+hipError_t launch_march3d_batch(const BatchGrid *grids, const int *prefix, int ngrids, bool src,
+                                int depth, int zseg, int nitems, hipStream_t st);
+template <typename R>
+int64_t march3d_batch_items(const Geom &g, int zseg, int depth);
+
+// Deep-halo block storage (k_deep.hip): refresh every block's H-deep frame
+// of state buffer s from the cells' owning blocks; fill the deep source
+// buffer bd (state layout) from the blocked source b (NULL: zeros).
+template <typename R>
+hipError_t launch_deep_exchange(const Geom &g, void *s, int H, hipStream_t st);
+template <typename R>
+hipError_t launch_deep_source(const Geom &g, const void *b, void *bd, int H, hipStream_t st);
 
 // Batched-solver bookkeeping (k_batch.hip).
 hipError_t launch_batch_init(int count, const BatchState &st, hipStream_t s);

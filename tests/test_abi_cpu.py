@@ -185,3 +185,33 @@ def test_noalloc_arguments_rejected_before_any_hip_call():
     # a problem that fits passes every check (2048^2 FP32 in 4x4 blocks)
     assert jb.jacobi_workspace_bytes(2, [2048, 2048], [4, 4], jb.JACOBI_F32) <= \
         jb.JACOBI_NOALLOC_MAX_BYTES
+
+
+def test_deep_halo_arguments():
+    # sizes: larger than the one-cell layout, growing with the frame depth
+    base = jb.jacobi_workspace_bytes(2, [8192, 8192], [16, 16], jb.JACOBI_F32)
+    d5 = jb.jacobi_deep_workspace_bytes(2, [8192, 8192], [16, 16], jb.JACOBI_F32, 5)
+    d13 = jb.jacobi_deep_workspace_bytes(2, [8192, 8192], [16, 16], jb.JACOBI_F32, 13)
+    assert base < d5 < d13
+    # the stored depth is rounded up (FP32: 1 + a multiple of 4): 6 -> 9 = 9
+    assert jb.jacobi_deep_workspace_bytes(2, [8192, 8192], [16, 16], jb.JACOBI_F32, 6) == \
+        jb.jacobi_deep_workspace_bytes(2, [8192, 8192], [16, 16], jb.JACOBI_F32, 9)
+    for halo, frag in ((0, "halo"), (65, "halo")):
+        msg = expect_status(jb.JACOBI_E_INVAL, jb.jacobi_deep_workspace_bytes, 2, [64, 64],
+                            [2, 2], jb.JACOBI_F32, halo)
+        assert frag in msg
+    # a frame deeper than a block is refused: 37 x 29 in 3 x 4 blocks has
+    # blocks of 5 nodes at the far edges
+    msg = expect_status(jb.JACOBI_E_INVAL, jb.jacobi_deep_workspace_bytes, 2, [37, 29], [3, 4],
+                        jb.JACOBI_F32, 9)
+    assert "exceeds the block extent" in msg
+    # one block per axis: any depth up to 64
+    assert jb.jacobi_deep_workspace_bytes(3, [8, 8, 8], [1, 1, 1], jb.JACOBI_F64, 64) > 0
+    L = jb.lib()
+    out = ctypes.c_void_p()
+    g, b = jb._arr64([64, 64]), jb._arr64([2, 2])
+    assert L.jacobi_deep_create(2, g, b, 0, 5, None, 1 << 30, None,
+                                ctypes.byref(out)) == jb.JACOBI_E_INVAL
+    assert L.jacobi_deep_create(2, g, b, 0, 5, ctypes.c_void_p(256), 16, None,
+                                ctypes.byref(out)) == jb.JACOBI_E_NOMEM
+    assert L.jacobi_get_halo(None, None) == jb.JACOBI_E_INVAL
