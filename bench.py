@@ -44,7 +44,8 @@ HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 FLOPS_PER_UPDATE = 5  # (W+E), (S+N), their sum, +b: 4 adds; *w: 1 mul
 REL_BOUND = 1e-5
-FORMS = ("batched", "adjoint", "poisson3d", "plain2d", "overdecomposition", "paper_domain_3d")
+FORMS = ("batched", "adjoint", "poisson3d", "plain2d", "overdecomposition", "paper_domain_3d",
+         "deep_halo")
 
 
 def parse():
@@ -448,6 +449,77 @@ def bench_paper_domain():
     return out, check
 
 
+def bench_deep_halo(fused):
+    """Deep-halo block storage (frames of H nodes exchanged once per pass of
+    up to H block-local sweeps) on the headline 2D workload (8192^2 FP32,
+    16x16 blocks, frames of 13, 1000 sweeps, residual every 50) and the 3D
+    one (512^3, 8^3 blocks, frames of 4 (stored 5), 200 sweeps, residual
+    every 20), against the fused forms on the same workloads; the final
+    states must equal the fused forms' bit for bit."""
+    import numpy as np
+    import torch
+    import paper_2303_02543_amd as jb
+    import synthetic
+    dev = torch.device("cuda:0")
+    out = {"workload": "deep-halo storage on the 8192^2 FP32 headline solve (frames of 13) and "
+                       "the 512^3 FP32/FP64 solves (frames of 4)"}
+
+    def run(grid, blocks, t_dt, f, U0, h2, K, R, halo):
+        s = jb.Solver(grid, blocks, t_dt, device=dev, halo=halo)
+        try:
+            fd, Ud = torch.from_numpy(f).to(dev), torch.from_numpy(U0).to(dev)
+            res = torch.empty(jb.residual_count(K, R), dtype=torch.float64, device=dev)
+
+            def step():
+                s.set_source(fd, h2)
+                s.set_state(Ud)
+                s.solve(K, R, res)
+            step()
+            torch.cuda.synchronize()
+            s.profile(True)
+            t0 = time.perf_counter()
+            step()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            p = s.profile_read(0)
+            s.profile(False)
+            final = _host(s.get_state())
+            return dt, p, final, s.halo(), s.get_tuning()
+        finally:
+            s.close()
+
+    n = N
+    U0, f = synthetic.poisson2d_gaussians(n)
+    dt, p, final, hs, tun = run((n, n), BLOCKS, torch.float32, f.astype(np.float32),
+                                U0.astype(np.float32), synthetic.spacing2(n), SWEEPS, CHECK_EVERY,
+                                13)
+    glups = float(n) ** 2 * SWEEPS / dt / 1e9
+    rec = {"halo": hs, "t_depth": tun[0], "rows": tun[1], "glups": round(glups, 1),
+           "pass_kernel_avg_ms": round(p["ms"] / p["launches"], 5),
+           "pass_kernel_share": round(p["ms"] * 1e-3 / dt, 4)}
+    if fused.get("headline") is not None:
+        rec["fused_glups"] = fused["headline"][0]
+        rec["ratio_vs_fused"] = round(glups / fused["headline"][0], 4)
+        rec["bit_identical_to_fused"] = bool(np.array_equal(final, fused["headline"][1]))
+    out["2d_f32"] = rec
+    n3 = 512
+    U0, f = synthetic.poisson3d_uniform(n3)
+    for name, np_dt, t_dt in (("f32", np.float32, torch.float32), ("f64", np.float64, torch.float64)):
+        dt, p, final, hs, tun = run((n3, n3, n3), (8, 8, 8), t_dt, f.astype(np_dt),
+                                    U0.astype(np_dt), synthetic.spacing2(n3), 200, 20, 4)
+        glups = float(n3) ** 3 * 200 / dt / 1e9
+        rec = {"halo": hs, "t_depth": tun[0], "zseg": tun[1], "glups": round(glups, 1),
+               "pass_kernel_avg_ms": round(p["ms"] / p["launches"], 5),
+               "pass_kernel_share": round(p["ms"] * 1e-3 / dt, 4)}
+        ref = fused.get("3d_" + name)
+        if ref is not None:
+            rec["fused_glups"] = ref[0]
+            rec["ratio_vs_fused"] = round(glups / ref[0], 4)
+            rec["bit_identical_to_fused"] = bool(np.array_equal(final, ref[1]))
+        out["3d_" + name] = rec
+    return out, None
+
+
 def _src_hash(path):
     with open(path, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
@@ -651,7 +723,9 @@ def cpu_baseline(U0_np, f_np, h2, target_seconds, full_max_seconds, gpu_final, c
     return out
 
 
-def run_form(name, plain_glups):
+def run_form(name, plain_glups, fused=None):
+    if name == "deep_halo":
+        return bench_deep_halo(fused or {})
     if name == "batched":
         return bench_batched(plain_glups)
     if name == "adjoint":
@@ -813,11 +887,16 @@ def main():
     s.close()
     checks = {}
     if not args.no_forms:
+        # final states of the fused forms, for the deep-halo form's identity check
+        fused = {"headline": (round(glups, 1), U_out.cpu().numpy())}
         for name in FORMS:
-            rec, chk = run_form(name, glups)
+            rec, chk = run_form(name, glups, fused)
             out[name] = rec
             if chk is not None:
                 checks[name] = chk
+            if name == "poisson3d":
+                for dn in ("f32", "f64"):
+                    fused["3d_" + dn] = (rec[dn]["glups"], chk["states"][dn])
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

@@ -770,7 +770,10 @@ int do_deep_sweep(jacobi_t h, int64_t n, double *res_first, bool sync_halos) {
     int depth = h->depth > 0 ? h->depth : default_depth(h);
     if (depth > h->halo) depth = h->halo;
     if (nd == 2) depth = pick_depth(h->dtype, depth);
-    const int rows = nd == 2 ? (h->rows > 0 ? h->rows : deep_rows<R>(h, depth)) : zseg_of(h);
+    // 3D: one z segment per small grid unless set (its 2(T-1) warm-up planes
+    // are paid once; measured fastest on 64^3 blocks)
+    const int rows = nd == 2 ? (h->rows > 0 ? h->rows : deep_rows<R>(h, depth))
+                             : (h->rows > 0 ? h->rows : h->g.e[2] + 2 * (h->halo - 1));
     int rc = deep_tables<R>(h, rows);
     if (rc) return rc;
     const int64_t nb = h->g.nblocks;
@@ -1298,7 +1301,12 @@ int jacobi_get_tuning(jacobi_t h, int *t_depth, int *rows, int *flags) {
     if (rc) return rc;
     if (!t_depth || !rows || !flags) return fail(JACOBI_E_INVAL, "output pointers must not be NULL");
     *t_depth = h->depth > 0 ? h->depth : default_depth(h);
-    *rows = h->rows > 0 ? h->rows : h->g.ndim == 3 ? zseg_of(h) : default_rows(h);
+    if (h->rows > 0)
+        *rows = h->rows;
+    else if (h->halo > 0 && h->g.ndim == 3)
+        *rows = h->g.e[2] + 2 * (h->halo - 1);  // deep-halo passes: one z segment per block
+    else
+        *rows = h->g.ndim == 3 ? zseg_of(h) : default_rows(h);
     *flags = h->flags;
     return JACOBI_OK;
 }
