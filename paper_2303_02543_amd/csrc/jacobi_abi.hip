@@ -134,9 +134,9 @@ int plan(int ndim, const int64_t *grid, const int64_t *blocks, int dtype, Geom *
     // workgroup of the standalone residual kernel
     size_t cap = ((size_t)g->n[0] / 32 + 2) * ((size_t)g->n[1] * g->n[2] / kMinRows + 2);
     if (ndim == 3) {
-        // 3D pass: 4 partials (one per wave) per work item of (strip of
-        // >= 24 output columns, >= 10 output rows, z segment of >= kMinRows
-        // planes), the smallest tiles of any depth
+        // 3D pass: 8 partials (one per wave) per work item of (strip of
+        // >= 24 output columns, >= 26 output rows, z segment of >= kMinRows
+        // planes), the smallest tiles of any depth; 4 per 10 rows bounds it
         const size_t c3 = ((size_t)g->n[0] / 24 + 2) * 4 * ((size_t)g->n[1] / 10 + 2) *
                           ((size_t)g->n[2] / kMinRows + 2);
         if (c3 > cap) cap = c3;

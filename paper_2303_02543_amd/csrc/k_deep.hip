@@ -88,12 +88,14 @@ __host__ __device__ inline int64_t frame_cells(const Geom &g, int H) {
 // node the neighbour holds in its own one-cell ring: a corner region along
 // the domain's side); on the domain's own sides the frame holds the block's
 // ring, which never changes, and cells beyond it, which no pass reads.
-// Grid: x over the frame cells of one block, y over blocks (strided).
+// Grid: x over the frame cells of one block, kDeepCells per thread (few
+// large workgroups: one cell per thread made the 3D exchange bound by
+// workgroup dispatch), y over blocks (strided).
+constexpr int kDeepCells = 16;
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_deep_exchange(Geom g, R *__restrict__ s, int H,
                                                        int per_block) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= per_block) return;
     for (int64_t blk = blockIdx.y; blk < g.nblocks; blk += gridDim.y) {
         const int bx = (int)(blk % g.nb[0]);
         const int by = (int)((blk / g.nb[0]) % g.nb[1]);
@@ -101,6 +103,9 @@ __global__ __launch_bounds__(256) void k_deep_exchange(Geom g, R *__restrict__ s
         const int ex = extent(g.n[0], g.e[0], bx);
         const int ey = extent(g.n[1], g.e[1], by);
         const int ez = g.ndim == 3 ? extent(g.n[2], g.e[2], bz) : 1;
+        for (int k = 0; k < kDeepCells; ++k) {
+        const int f = (blockIdx.x * kDeepCells + k) * blockDim.x + threadIdx.x;
+        if (f >= per_block) break;
         int lx, ly, lz;
         if (!frame_cell(g, H, ex, ey, ez, f, lx, ly, lz)) continue;
         // the owner along each axis is the adjacent block or this one (the
@@ -130,6 +135,7 @@ __global__ __launch_bounds__(256) void k_deep_exchange(Geom g, R *__restrict__ s
         const int64_t ob = ((int64_t)o[2] * g.nb[1] + o[1]) * g.nb[0] + o[0];
         if (skip || ob == blk) continue;  // beyond the ring, or the block's own ring
         s[local_offset(g, blk, lx, ly, lz)] = s[local_offset(g, ob, l[0], l[1], l[2])];
+        }
     }
 }
 
@@ -162,7 +168,7 @@ template <typename R>
 hipError_t launch_deep_exchange(const Geom &g, void *s, int H, hipStream_t st) {
     const int64_t per = frame_cells(g, H);
     if (per > 0x7fffffff - 255) return hipErrorInvalidValue;
-    const unsigned gx = (unsigned)((per + 255) / 256);
+    const unsigned gx = (unsigned)((per + 256 * kDeepCells - 1) / (256 * kDeepCells));
     const unsigned gy = (unsigned)(g.nblocks < 65535 ? g.nblocks : 65535);
     hipLaunchKernelGGL(k_deep_exchange<R>, dim3(gx, gy), dim3(256), 0, st, g, (R *)s, H, (int)per);
     return hipGetLastError();

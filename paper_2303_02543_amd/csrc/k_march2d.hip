@@ -263,14 +263,24 @@ __device__ __forceinline__ void m2_read_src(const MLane &L, MRegs<R, T, P> &m, c
 // Level S of step J (row r = base + J): computes row r - S from the three
 // newest rows of level S - 1 (level 0 = the loaded rows).  All ring slots are
 // compile-time constants so the rings live in registers.
-template <typename R, int T, int P, int MODE, bool EDGE, bool RES, int J, int S>
+// Deepest level worth computing at step J of unrolled group G of a tile
+// (G < 0: past the tile's first two groups).  Level S of the tile's step j
+// reads level-0 rows back to r0 + j - 2S, so it holds a row of the output's
+// dependence cone only from j = 2S on; earlier levels are skipped.
+template <int T, int U, int G, int J>
+constexpr int m2_lmax() {
+    return G < 0 ? T : ((G * U + J) / 2 < T ? (G * U + J) / 2 : T);
+}
+
+template <typename R, int T, int P, int MODE, bool EDGE, bool RES, int J, int S, int G = -1>
 __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
                                          double *__restrict__ gacc, const MLane &L, MRegs<R, T, P> &m, const int r,
                                          const Cur &sc, const int sr) {
     using M = M2<R, T, P>;
     constexpr int V = M::V;
     constexpr bool SRC = MODE == MODE_POISSON;
-    if constexpr (S <= T) {
+    constexpr int LMAX = m2_lmax<T, M::U, G, J>();
+    if constexpr (S <= LMAX) {
         const int y = r - S;
         const int ny = g.n[1];
         // value copies (register renames): pointers into the rings would
@@ -292,7 +302,7 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
         if constexpr (SRC) {
 #pragma unroll
             for (int v = 0; v < V; ++v) bv[v] = m.bn[S & 1][v];
-            if constexpr (S < T) m2_read_src<R, T, P, S + 1>(L, m, sr);
+            if constexpr (S < LMAX) m2_read_src<R, T, P, S + 1>(L, m, sr);
         }
         R out[V];
         if (!EDGE || (y >= 0 && y < ny)) {
@@ -356,11 +366,11 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
                 }
             }
         }
-        m2_level<R, T, P, MODE, EDGE, RES, J, S + 1>(g, uout, gacc, L, m, r, sc, sr);
+        m2_level<R, T, P, MODE, EDGE, RES, J, S + 1, G>(g, uout, gacc, L, m, r, sc, sr);
     }
 }
 
-template <typename R, int T, int P, int MODE, bool EDGE, bool RES, int J>
+template <typename R, int T, int P, int MODE, bool EDGE, bool RES, int J, int G = -1>
 __device__ __forceinline__ void m2_steps(const Geom &g, const R *__restrict__ uin,
                                          R *__restrict__ uout, const R *__restrict__ bsrc,
                                          double *__restrict__ gacc, const MLane &L, MRegs<R, T, P> &m, const int base, Cur &lc,
@@ -395,11 +405,13 @@ __device__ __forceinline__ void m2_steps(const Geom &g, const R *__restrict__ ui
             for (int v = 0; v < V; ++v) v0[v] = m.l0[J % M::LR][v];
             m2_accumulate<R, T, P, MODE, EDGE, J % M::RA, T == 1>(g, gacc, L, m, r, v0);
         }
-        if constexpr (MODE == MODE_POISSON) m2_read_src<R, T, P, 1>(L, m, sr);
-        m2_level<R, T, P, MODE, EDGE, RES, J, 1>(g, uout, gacc, L, m, r, sc, sr);
+        if constexpr (MODE == MODE_POISSON && m2_lmax<T, M::U, G, J>() >= 1)
+            m2_read_src<R, T, P, 1>(L, m, sr);
+        m2_level<R, T, P, MODE, EDGE, RES, J, 1, G>(g, uout, gacc, L, m, r, sc, sr);
         sc.advance(g);
         sr = sr + 1 == M::RB ? 0 : sr + 1;
-        m2_steps<R, T, P, MODE, EDGE, RES, J + 1>(g, uin, uout, bsrc, gacc, L, m, base, lc, sc, sr);
+        m2_steps<R, T, P, MODE, EDGE, RES, J + 1, G>(g, uin, uout, bsrc, gacc, L, m, base, lc, sc,
+                                                     sr);
     }
 }
 
@@ -435,7 +447,22 @@ __device__ __forceinline__ void m2_body(const Geom &g, const R *__restrict__ uin
     if constexpr (P > 1) m2_load<R, T, P, MODE, EDGE, 1, 1 % S::BQ, 1 % S::RA>(g, uin, bsrc, gacc, L, m, lc);
     if constexpr (P > 2) m2_load<R, T, P, MODE, EDGE, 2, 2 % S::BQ, 2 % S::RA>(g, uin, bsrc, gacc, L, m, lc);
     int sr = 0;  // LDS source slot of the current row
-    for (int base = r0; base <= L.r1; base += S::U)
+    int base = r0;
+    if constexpr (MODE != MODE_ADJOINT && T > 1) {
+        // the tile's first group (and, from depth 7 on, its second) skip the
+        // levels still outside the output's dependence cone (the adjoint
+        // pass accumulates every level it holds, so it runs them all)
+        m2_steps<R, T, P, MODE, EDGE, RES, 0, 0>(g, uin, uout, bsrc, gacc, L, m, base, lc, sc, sr);
+        base += S::U;
+        if constexpr (T > S::U / 2) {
+            if (base <= L.r1) {
+                m2_steps<R, T, P, MODE, EDGE, RES, 0, 1>(g, uin, uout, bsrc, gacc, L, m, base, lc,
+                                                         sc, sr);
+                base += S::U;
+            }
+        }
+    }
+    for (; base <= L.r1; base += S::U)
         m2_steps<R, T, P, MODE, EDGE, RES, 0>(g, uin, uout, bsrc, gacc, L, m, base, lc, sc, sr);
     if constexpr (RES) {
         const double a = wave_sum(m.acc);

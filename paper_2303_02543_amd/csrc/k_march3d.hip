@@ -8,7 +8,7 @@
 //   s = ((W + E) + (S + N)) + (B + F);  u' = (s + b) * fl(1/6)
 // with no FMA contraction, so every schedule gives the same bits.
 //
-// A workgroup of 4 waves holds 16 rows by 16 lanes x V elements along x (one
+// A workgroup of 8 waves holds 32 rows by 16 lanes x V elements along x (one
 // 16-lane row of a wave per grid row; 64 columns in FP32, 32 in FP64) and
 // marches along z through a segment of planes.  For the 64^3 blocks of the
 // workloads a wave's 4 rows lie in one block, so every load instruction reads
@@ -25,7 +25,7 @@
 // per row end) and the two rows just outside it (one load each), so it is
 // valid on the whole tile, and level s on the tile less s - 1 cells on every
 // side in x and y.  Level T is the pass's output on the inner tile: rows
-// T-1 .. 16-T, columns A0 .. A0+OW-1 (chunk-aligned).  A z segment costs
+// T-1 .. 32-T, columns A0 .. A0+OW-1 (chunk-aligned).  A z segment costs
 // 2(T-1) extra planes of warm-up.
 //
 // The Dirichlet ring keeps its values at every level: a level on a ring
@@ -40,7 +40,9 @@
 
 namespace jac {
 
-constexpr int kM3Rows = 16;  // rows held per work item (4 waves x 4 rows)
+constexpr int kM3Waves = 8;              // waves per work item (workgroup)
+constexpr int kM3Threads = 64 * kM3Waves;
+constexpr int kM3Rows = 4 * kM3Waves;    // rows held per work item (4 per wave)
 
 template <typename R, int T>
 struct M3 {
@@ -315,10 +317,10 @@ __device__ __forceinline__ void m3_body(const Geom &g, const R *__restrict__ uin
     }
 }
 
-// Work item (one workgroup of 4 waves) number `item` of a grid cut into
+// Work item (one workgroup of 8 waves) number `item` of a grid cut into
 // ngrp row groups (fastest), nstrips column strips and z segments of `zseg`
 // output planes; wave q takes rows y0+4q .. y0+4q+3.  The residual partials
-// are per wave: work item i owns partials 4i .. 4i+3 (res points at them).
+// are per wave: work item i owns partials 8i .. 8i+7 (res points at them).
 template <typename R, int T, int MODE, bool RES>
 __device__ __forceinline__ void m3_item(const Geom &g, const R *__restrict__ uin,
                                         R *__restrict__ uout, const R *__restrict__ bsrc,
@@ -352,7 +354,7 @@ __device__ __forceinline__ void m3_item(const Geom &g, const R *__restrict__ uin
     if (wv == 0 && ry == 0) {
         L.hk = 0;
         L.h_off = xy_part(g, cl, clampy(y0 - 1));
-    } else if (wv == 3 && ry == 3) {
+    } else if (wv == kM3Waves - 1 && ry == 3) {
         L.hk = kM3Rows + 1;
         L.h_off = xy_part(g, cl, clampy(y0 + kM3Rows));
     }
@@ -373,7 +375,7 @@ __device__ __forceinline__ void m3_item(const Geom &g, const R *__restrict__ uin
     }
     const int oz0 = zs * zseg;
     const int oz1 = oz0 + zseg < g.n[2] ? oz0 + zseg : g.n[2];
-    double *slot = RES ? res + (int64_t)item * 4 + wv : nullptr;
+    double *slot = RES ? res + (int64_t)item * kM3Waves + wv : nullptr;
     const bool edge = a < 0 || a + W > nx || y0 < 0 || y0 + kM3Rows > ny;
     const bool ntb = nt != 0;
     if (edge)
@@ -383,12 +385,12 @@ __device__ __forceinline__ void m3_item(const Geom &g, const R *__restrict__ uin
 }
 
 template <typename R, int T, int MODE, bool RES>
-__global__ __launch_bounds__(256) void k_march3d(Geom g, const R *__restrict__ uin,
+__global__ __launch_bounds__(kM3Threads) void k_march3d(Geom g, const R *__restrict__ uin,
                                                  R *__restrict__ uout,
                                                  const R *__restrict__ bsrc,
                                                  double *__restrict__ res, int nstrips, int ngrp,
                                                  int zseg, int nitems, int nt) {
-    // per level 0 .. T-1: two plane buffers of rows y0-1 .. y0+16
+    // per level 0 .. T-1: two plane buffers of rows y0-1 .. y0+kM3Rows
     __shared__ Chunk<R, M3<R, T>::V> sh[T][2][kM3Rows + 2][16];
     const int item = xcd_logical_block(blockIdx.x, gridDim.x);
     if (item >= nitems) return;  // whole workgroup
@@ -400,7 +402,7 @@ __global__ __launch_bounds__(256) void k_march3d(Geom g, const R *__restrict__ u
 // belongs to grid gi with prefix[gi] <= w < prefix[gi+1]; every grid's input
 // is u[0] and its output u[1].
 template <typename R, int T, int MODE>
-__global__ __launch_bounds__(256) void k_march3d_batch(const BatchGrid *__restrict__ grids,
+__global__ __launch_bounds__(kM3Threads) void k_march3d_batch(const BatchGrid *__restrict__ grids,
                                                        const int *__restrict__ prefix,
                                                        int ngrids, int zseg, int nitems) {
     using M = M3<R, T>;
@@ -433,7 +435,7 @@ template <typename R, int T>
 static int64_t m3_work_items(const Geom &g, int zseg) {
     int ns, ng, nz;
     m3_shape<R, T>(g, zseg, ns, ng, nz);
-    return 4 * (int64_t)ns * ng * nz;
+    return kM3Waves * (int64_t)ns * ng * nz;
 }
 
 template <typename R, int T>
@@ -441,13 +443,13 @@ static hipError_t m3_launch(const Geom &g, const void *uin, void *uout, const vo
                             double *res, int zseg, hipStream_t st, int64_t *nwork_out, int nt) {
     int ns, ng, nz;
     m3_shape<R, T>(g, zseg, ns, ng, nz);
-    const int64_t nwaves = 4 * (int64_t)ns * ng * nz;
+    const int64_t nwaves = kM3Waves * (int64_t)ns * ng * nz;
     if (nwork_out) *nwork_out = nwaves;
     if (nwaves > 0x7fffffff - 3) return hipErrorInvalidValue;
-    const int items = (int)(nwaves / 4);
+    const int items = (int)(nwaves / kM3Waves);
     const R *bb = (const R *)b;
 #define JAC_M3(MODEV, RESV)                                                                   \
-    hipLaunchKernelGGL((k_march3d<R, T, MODEV, RESV>), dim3(items), dim3(256), 0, st, g,      \
+    hipLaunchKernelGGL((k_march3d<R, T, MODEV, RESV>), dim3(items), dim3(kM3Threads), 0, st, g,      \
                        (const R *)uin, (R *)uout, bb, res, ns, ng, zseg, items, nt)
     if (b && res)
         JAC_M3(1, true);
@@ -466,20 +468,20 @@ static hipError_t m3b_launch(const BatchGrid *grids, const int *prefix, int ngri
                              int zseg, int nitems, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
     if (src)
-        hipLaunchKernelGGL((k_march3d_batch<R, T, 1>), dim3(nitems), dim3(256), 0, st, grids,
+        hipLaunchKernelGGL((k_march3d_batch<R, T, 1>), dim3(nitems), dim3(kM3Threads), 0, st, grids,
                            prefix, ngrids, zseg, nitems);
     else
-        hipLaunchKernelGGL((k_march3d_batch<R, T, 0>), dim3(nitems), dim3(256), 0, st, grids,
+        hipLaunchKernelGGL((k_march3d_batch<R, T, 0>), dim3(nitems), dim3(kM3Threads), 0, st, grids,
                            prefix, ngrids, zseg, nitems);
     return hipGetLastError();
 }
 
-int march3d_max_depth() { return 4; }
+int march3d_max_depth() { return 5; }
 
 template <typename R>
 int64_t march3d_batch_items(const Geom &g, int zseg, int depth) {
     const int64_t w = march3d_work_items<R>(g, zseg, depth);
-    return w < 0 ? w : w / 4;
+    return w < 0 ? w : w / kM3Waves;
 }
 
 template <typename R>
@@ -490,6 +492,7 @@ hipError_t launch_march3d_batch(const BatchGrid *grids, const int *prefix, int n
     case 2: return m3b_launch<R, 2>(grids, prefix, ngrids, src, zseg, nitems, st);
     case 3: return m3b_launch<R, 3>(grids, prefix, ngrids, src, zseg, nitems, st);
     case 4: return m3b_launch<R, 4>(grids, prefix, ngrids, src, zseg, nitems, st);
+    case 5: return m3b_launch<R, 5>(grids, prefix, ngrids, src, zseg, nitems, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -502,6 +505,7 @@ int64_t march3d_work_items(const Geom &g, int zseg, int depth) {
     case 2: return m3_work_items<R, 2>(g, zseg);
     case 3: return m3_work_items<R, 3>(g, zseg);
     case 4: return m3_work_items<R, 4>(g, zseg);
+    case 5: return m3_work_items<R, 5>(g, zseg);
     default: return -1;
     }
 }
@@ -514,6 +518,7 @@ hipError_t launch_march3d(const Geom &g, const void *uin, void *uout, const void
     case 2: return m3_launch<R, 2>(g, uin, uout, b, res, zseg, st, nwork_out, nt);
     case 3: return m3_launch<R, 3>(g, uin, uout, b, res, zseg, st, nwork_out, nt);
     case 4: return m3_launch<R, 4>(g, uin, uout, b, res, zseg, st, nwork_out, nt);
+    case 5: return m3_launch<R, 5>(g, uin, uout, b, res, zseg, st, nwork_out, nt);
     default: return hipErrorInvalidValue;
     }
 }

@@ -92,7 +92,7 @@ int64_t march2d_batch_work(const Geom &g, int depth, int rows);
 // `depth` 3D sweeps in one pass over the whole grid (k_march3d.hip), reading
 // face neighbours' cells from their owning blocks; zseg output planes per
 // work item.  uout may be NULL (residual only); res: one partial per wave
-// (4 per work item) or NULL.  depth in 1 .. march3d_max_depth().
+// (8 per work item) or NULL.  depth in 1 .. march3d_max_depth().
 template <typename R>
 hipError_t launch_march3d(const Geom &g, const void *uin, void *uout, const void *b, double *res,
                           int zseg, hipStream_t st, int64_t *nwork, int nt = 0, int depth = 1);
