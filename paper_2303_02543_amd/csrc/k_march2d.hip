@@ -248,13 +248,14 @@ __device__ __forceinline__ void m2_accumulate(const Geom &g, double *__restrict_
     }
 }
 
-// Read the source row of level S (row r - S) from the wave's LDS ring into
-// bn[S & 1].  Issued one level before its use, so the LDS latency overlaps
-// the arithmetic of the level in between.
-template <typename R, int T, int P, int S>
+// Read the source row of level S from the wave's LDS ring into bn[S & 1]:
+// the row K steps back (K = S: row r - S, for level S of this step; K = 0:
+// row r, for level 1 of the next step).  Issued one level before its use, so
+// the LDS latency overlaps the arithmetic of the level in between.
+template <typename R, int T, int P, int S, int K = S>
 __device__ __forceinline__ void m2_read_src(const MLane &L, MRegs<R, T, P> &m, const int sr) {
     using M = M2<R, T, P>;
-    const int slot = sr - S < 0 ? sr - S + M::RB : sr - S;
+    const int slot = sr - K < 0 ? sr - K + M::RB : sr - K;
     const Chunk<R, M::V> c = static_cast<const Chunk<R, M::V> *>(L.bs)[slot * 64];
 #pragma unroll
     for (int v = 0; v < M::V; ++v) m.bn[S & 1][v] = c.v[v];
@@ -270,6 +271,12 @@ __device__ __forceinline__ void m2_read_src(const MLane &L, MRegs<R, T, P> &m, c
 template <int T, int U, int G, int J>
 constexpr int m2_lmax() {
     return G < 0 ? T : ((G * U + J) / 2 < T ? (G * U + J) / 2 : T);
+}
+
+// Whether the step after step J of group G computes level 1.
+template <int T, int U, int G, int J>
+constexpr bool m2_next_l1() {
+    return J + 1 == U || m2_lmax<T, U, G, J + 1>() >= 1;
 }
 
 template <typename R, int T, int P, int MODE, bool EDGE, bool RES, int J, int S, int G = -1>
@@ -302,7 +309,14 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
         if constexpr (SRC) {
 #pragma unroll
             for (int v = 0; v < V; ++v) bv[v] = m.bn[S & 1][v];
-            if constexpr (S < LMAX) m2_read_src<R, T, P, S + 1>(L, m, sr);
+            if constexpr (S < LMAX)
+                m2_read_src<R, T, P, S + 1>(L, m, sr);
+            else if constexpr (m2_next_l1<T, M::U, G, J>())
+                m2_read_src<R, T, P, 1, 0>(L, m, sr);  // the next step's level 1: this row
+            // keep the read ahead of this level's arithmetic: left to itself
+            // the scheduler sinks it to just before its use, a few
+            // instructions on, and every level then waits for LDS
+            __builtin_amdgcn_sched_barrier(0);
         }
         R out[V];
         if (!EDGE || (y >= 0 && y < ny)) {
@@ -405,8 +419,11 @@ __device__ __forceinline__ void m2_steps(const Geom &g, const R *__restrict__ ui
             for (int v = 0; v < V; ++v) v0[v] = m.l0[J % M::LR][v];
             m2_accumulate<R, T, P, MODE, EDGE, J % M::RA, T == 1>(g, gacc, L, m, r, v0);
         }
-        if constexpr (MODE == MODE_POISSON && m2_lmax<T, M::U, G, J>() >= 1)
-            m2_read_src<R, T, P, 1>(L, m, sr);
+        // level 1's source row was read by the last level of the step before;
+        // a step that computes no level reads the next step's row itself
+        if constexpr (MODE == MODE_POISSON && m2_lmax<T, M::U, G, J>() == 0 &&
+                      m2_next_l1<T, M::U, G, J>())
+            m2_read_src<R, T, P, 1, 0>(L, m, sr);
         m2_level<R, T, P, MODE, EDGE, RES, J, 1, G>(g, uout, gacc, L, m, r, sc, sr);
         sc.advance(g);
         sr = sr + 1 == M::RB ? 0 : sr + 1;
@@ -462,6 +479,9 @@ __device__ __forceinline__ void m2_body(const Geom &g, const R *__restrict__ uin
             }
         }
     }
+    // without the warm-up groups the first step computes level 1 (its row
+    // lies before the tile and is not an output)
+    if constexpr (MODE == MODE_POISSON && T == 1) m2_read_src<R, T, P, 1>(L, m, sr);
     for (; base <= L.r1; base += S::U)
         m2_steps<R, T, P, MODE, EDGE, RES, 0>(g, uin, uout, bsrc, gacc, L, m, base, lc, sc, sr);
     if constexpr (RES) {
