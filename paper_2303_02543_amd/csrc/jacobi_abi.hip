@@ -1946,7 +1946,7 @@ int jacobi_batch_autotune(jacobi_batch_t b, int64_t check_every, int *t_depth, i
     int rc = batch_check(b);
     if (rc) return rc;
     if (check_every < 1 || check_every > (1 << 20)) return fail(JACOBI_E_INVAL, "check_every out of range");
-    static const int kRows[] = {16, 24, 32, 48, 64, 96, 128, 192};
+    static const int kRows[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 320, 384};
     const int *list;
     const int nd = jac::march2d_depths(b->dtype, &list);
     hipEvent_t e0, e1;

@@ -26,11 +26,13 @@
 //
 // Every load is unconditional: a load issued on only some paths would turn
 // the next step's wait for its data into a wait for every load in flight.
-// Tiles that reach the Dirichlet ring or the rows beyond it (first/last
-// strip, first/last row segment) run an edge copy of the body, which reads an
-// in-bounds stand-in address where a row or column lies outside the grid,
-// zeroes what it read there, and keeps ring cells at their values.  Interior
-// tiles run a copy with no row or column tests at all.
+// Tiles that reach the Dirichlet ring or the rows beyond it run an edge copy
+// of the body, which reads an in-bounds stand-in address where a row or
+// column lies beyond the ring and keeps ring cells at their values at every
+// level; what lies beyond the ring only ever feeds ring cells, so it is
+// never cleared.  There are three copies: row and column tests (tiles of a
+// strip that reaches the ring in x), row tests only (the other tiles that
+// reach it in y), and none (interior tiles).
 #include <hip/hip_runtime.h>
 
 #include "device_util.h"
@@ -69,30 +71,35 @@ struct M2 {
 };
 
 // Tiling of a pass over an nx x ny grid.  Strips of OW output columns;
-// the inner strips 1 .. ns-2 are cut into a band of he rows at the top, one
+// the inner strips 1 .. ns-2 are cut into a band of hb rows at the top, one
 // at the bottom, and tiles of `rows` rows between them; the outer strips 0
-// and ns-1 into tiles of he rows throughout.  A tile that reaches the
-// Dirichlet ring (an outer strip, or a band) runs the edge body, which
-// issues about 1.6x the instructions per step of the interior body (and
-// takes about 1.46x the time: the measured fastest band height on MI355X
-// lies between fractions 5/8 and 3/4 of the interior tile below), and a tile
-// of h rows takes h + 2T steps; with (he + 2T) = (rows + 2T) * 11/16 the
-// edge tiles take about as long as the interior ones, so a pass, whose
-// tiles all run as one generation of waves, is not held up by its edges.
+// and ns-1 into tiles of ho rows throughout.  A tile of h rows takes h + 2T
+// steps.  Tiles that reach the Dirichlet ring run an edge copy of the step:
+// the bands one with row tests (~1.2x the VALU instructions of the interior
+// step), the outer strips one with row and column tests (~1.4x).  Their
+// heights follow from (h + 2T) = (rows + 2T) * F / 16, with F = kBand16 for
+// the bands and kOuter16 for the outer strips, so edge tiles take about as
+// long as interior ones and a pass, whose tiles all run as one generation
+// of waves, is not held up by its edges.
+constexpr int kBand16 = 14, kOuter16 = 12;
 struct M2Tiles {
-    int ns, he, sa, sb, na, nb;  // strips, band height, tiles per inner / outer strip, inner / outer strips
-    int64_t ninner, nwork;       // tiles of the inner strips, all tiles
+    int ns, hb, ho, sa, sb, na, nb;  // strips, band / outer tile height, tiles per inner / outer strip, inner / outer strips
+    int64_t ninner, nwork;           // tiles of the inner strips, all tiles
 };
+__host__ __device__ inline int m2_edge_rows(int rows, int T, int f16, int ny) {
+    const int lo = rows < 8 ? rows : 8;
+    int h = (rows + 2 * T) * f16 / 16 - 2 * T;
+    h = h > lo ? h : lo;
+    return h < ny ? h : ny;
+}
 __host__ __device__ inline M2Tiles m2_tiles(int nx, int ny, int ow, int rows, int T) {
     M2Tiles t;
     t.ns = (nx + ow - 1) / ow;
-    const int lo = rows < 8 ? rows : 8;
-    int he = (rows + 2 * T) * 11 / 16 - 2 * T;
-    he = he > lo ? he : lo;
-    t.he = he < ny ? he : ny;
-    const int mid = ny - 2 * t.he;
-    t.sa = ny <= t.he ? 1 : 2 + (mid > 0 ? (mid + rows - 1) / rows : 0);
-    t.sb = (ny + t.he - 1) / t.he;
+    t.hb = m2_edge_rows(rows, T, kBand16, ny);
+    t.ho = m2_edge_rows(rows, T, kOuter16, ny);
+    const int mid = ny - 2 * t.hb;
+    t.sa = ny <= t.hb ? 1 : 2 + (mid > 0 ? (mid + rows - 1) / rows : 0);
+    t.sb = (ny + t.ho - 1) / t.ho;
     t.na = t.ns > 2 ? t.ns - 2 : 0;
     t.nb = t.ns < 2 ? t.ns : 2;
     t.ninner = (int64_t)t.na * t.sa;
@@ -108,20 +115,20 @@ __host__ __device__ inline void m2_tile(const M2Tiles &t, int ny, int rows, int6
         const int seg = (int)(w / t.na);
         if (seg == 0) {
             oy0 = 0;
-            oy1 = t.he;
+            oy1 = t.hb;
         } else if (seg == t.sa - 1) {
-            oy0 = ny - t.he > t.he ? ny - t.he : t.he;
+            oy0 = ny - t.hb > t.hb ? ny - t.hb : t.hb;
             oy1 = ny;
         } else {
-            oy0 = t.he + (seg - 1) * rows;
-            oy1 = oy0 + rows < ny - t.he ? oy0 + rows : ny - t.he;
+            oy0 = t.hb + (seg - 1) * rows;
+            oy1 = oy0 + rows < ny - t.hb ? oy0 + rows : ny - t.hb;
         }
     } else {
         const int64_t v = w - t.ninner;
         strip = t.nb == 2 && (v & 1) ? t.ns - 1 : 0;
         const int seg = (int)(t.nb == 2 ? v >> 1 : v);
-        oy0 = seg * t.he;
-        oy1 = oy0 + t.he < ny ? oy0 + t.he : ny;
+        oy0 = seg * t.ho;
+        oy1 = oy0 + t.ho < ny ? oy0 + t.ho : ny;
     }
 }
 
@@ -174,10 +181,11 @@ struct MRegs {
 
 struct MLane {
     uint32_t lane_b, edge_b, src_b;  // byte offsets of the lane's chunk / edge / source
-    bool ld, ldb, lde;
-    bool upd[8];                     // per-element: interior column (edge tiles)
-    bool st[8];                      // per-element: interior output column (edge tiles)
+    bool upd[8];                     // per element: interior column (column-edge tiles)
+    bool st[8];                      // per element: interior output column (column-edge tiles)
     bool out_lane;                   // lane holds output columns
+    bool st_all;                     // every column of the lane is an interior output
+    bool st_part;                    // some but not all are (the east ring's lane)
     bool nt;                         // non-temporal output stores
     int c;                           // global column of the lane's first element
     void *bs;                        // this lane's slot 0 of the wave's LDS source ring
@@ -186,7 +194,7 @@ struct MLane {
 
 // Issue the loads of row lc.y into level-0 slot SL, source register slot SQ
 // and (adjoint pass) accumulator slot SA, then advance the cursor.
-template <typename R, int T, int P, int MODE, bool EDGE, int SL, int SQ, int SA>
+template <typename R, int T, int P, int MODE, int EK, int SL, int SQ, int SA>
 __device__ __forceinline__ void m2_load(const Geom &g, const R *__restrict__ uin,
                                         const R *__restrict__ bsrc,
                                         const double *__restrict__ gacc, const MLane &L,
@@ -205,20 +213,20 @@ __device__ __forceinline__ void m2_load(const Geom &g, const R *__restrict__ uin
             m.ga[SA][v] = in ? gacc[(int64_t)y * nx + (L.c + v)] : 0.0;
         }
     }
-    const bool row_ok = !EDGE || (y >= -1 && y <= ny);
+    // rows and columns beyond the ring are read from in-bounds stand-ins and
+    // kept as they come: they only ever feed ring cells, which every level
+    // keeps at their values
+    const bool row_ok = !(EK & 1) || (y >= -1 && y <= ny);
     const R *row = uin + (row_ok ? lc.su : (int64_t)g.pitch);
     const C c = at<C>(row, L.lane_b);
-    const R e = at<R>(row, L.edge_b);
-    const bool ok = !EDGE || (row_ok && L.ld);
 #pragma unroll
-    for (int v = 0; v < V; ++v) m.l0[SL][v] = ok ? c.v[v] : (R)0;
-    m.e0[SL] = (!EDGE || (row_ok && L.lde)) ? e : (R)0;
+    for (int v = 0; v < V; ++v) m.l0[SL][v] = c.v[v];
+    m.e0[SL] = at<R>(row, L.edge_b);
     if constexpr (SRC) {
-        const bool brow = !EDGE || (y >= 0 && y < ny);
+        const bool brow = !(EK & 1) || (y >= 0 && y < ny);
         const C cb = at<C>(bsrc + (brow ? lc.sb : (int64_t)0), L.src_b);
-        const bool okb = !EDGE || (brow && L.ldb);
 #pragma unroll
-        for (int v = 0; v < V; ++v) m.bq[SQ][v] = okb ? cb.v[v] : (R)0;
+        for (int v = 0; v < V; ++v) m.bq[SQ][v] = cb.v[v];
     }
     lc.advance(g);
 }
@@ -226,13 +234,13 @@ __device__ __forceinline__ void m2_load(const Geom &g, const R *__restrict__ uin
 // Adjoint pass: add w * (level values of row y) into the row's accumulator,
 // in the order of decreasing sweep index; store the accumulator when its last
 // level (T - 1) has been added.
-template <typename R, int T, int P, int MODE, bool EDGE, int SA, bool LAST>
+template <typename R, int T, int P, int MODE, int EK, int SA, bool LAST>
 __device__ __forceinline__ void m2_accumulate(const Geom &g, double *__restrict__ gacc,
                                               const MLane &L, MRegs<R, T, P> &m, const int y,
                                               const R (&val)[M2<R, T, P>::V]) {
     constexpr int V = M2<R, T, P>::V;
     if constexpr (MODE == MODE_ADJOINT) {
-        if (!EDGE || (y >= 0 && y < g.n[1])) {
+        if (!(EK & 1) || (y >= 0 && y < g.n[1])) {
             const R w = (R)0.25;
 #pragma unroll
             for (int v = 0; v < V; ++v) m.ga[SA][v] += (double)(w * val[v]);
@@ -240,7 +248,7 @@ __device__ __forceinline__ void m2_accumulate(const Geom &g, double *__restrict_
                 double *row = gacc + (int64_t)y * g.n[0] + L.c;
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    const bool mine = EDGE ? L.st[v] : L.out_lane;
+                    const bool mine = (EK & 2) ? L.st[v] : L.out_lane;
                     if (mine) row[v] = m.ga[SA][v];
                 }
             }
@@ -279,7 +287,7 @@ constexpr bool m2_next_l1() {
     return J + 1 == U || m2_lmax<T, U, G, J + 1>() >= 1;
 }
 
-template <typename R, int T, int P, int MODE, bool EDGE, bool RES, int J, int S, int G = -1>
+template <typename R, int T, int P, int MODE, int EK, bool RES, int J, int S, int G = -1>
 __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
                                          double *__restrict__ gacc, const MLane &L, MRegs<R, T, P> &m, const int r,
                                          const Cur &sc, const int sr) {
@@ -319,7 +327,7 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
             __builtin_amdgcn_sched_barrier(0);
         }
         R out[V];
-        if (!EDGE || (y >= 0 && y < ny)) {
+        {
             R eo = (R)0;
             if constexpr (S == 1) eo = m.e0[(J + M::LR - 1) % M::LR];
             const R left = shift_up(eo, cen[V - 1]);
@@ -343,48 +351,54 @@ __device__ __forceinline__ void m2_level(const Geom &g, R *__restrict__ uout,
                             ((double)Wv + (double)Ev) + ((double)up[v] + (double)dn[v]);
                         const double bd = SRC ? (double)bv[v] : 0.0;
                         const double rr = bd - (4.0 * (double)cen[v] - sd);
-                        const bool mine = EDGE ? L.st[v] : L.out_lane;
+                        const bool mine = (EK & 2) ? L.st[v] : L.out_lane;
                         m.acc += mine ? rr * rr : 0.0;
                     }
                 }
-                // ring cells (and cells beyond the ring) keep their values
-                if constexpr (EDGE) o = L.upd[v] ? o : cen[v];
+                // ring columns (and columns beyond them) keep their values
+                if constexpr ((EK & 2) != 0) o = L.upd[v] ? o : cen[v];
                 out[v] = o;
             }
-        } else {
+        }
+        // ring rows (and rows beyond them) keep their values
+        if constexpr ((EK & 1) != 0) {
+            if (y < 0 || y >= ny) {
 #pragma unroll
-            for (int v = 0; v < V; ++v) out[v] = cen[v];
+                for (int v = 0; v < V; ++v) out[v] = cen[v];
+            }
         }
         if constexpr (S < T) {
 #pragma unroll
             for (int v = 0; v < V; ++v) m.lv[S - 1][J % 3][v] = out[v];
-            m2_accumulate<R, T, P, MODE, EDGE, (J - S + 2 * M::RA) % M::RA, S == T - 1>(g, gacc, L,
+            m2_accumulate<R, T, P, MODE, EK, (J - S + 2 * M::RA) % M::RA, S == T - 1>(g, gacc, L,
                                                                                      m, y, out);
         } else {
             if (uout && y >= L.oy0 && y < L.oy1) {
                 R *row = uout + sc.su;
-                if constexpr (!EDGE) {
-                    if (L.out_lane) {
-                        Chunk<R, V> o;
+                Chunk<R, V> o;
 #pragma unroll
-                        for (int v = 0; v < V; ++v) o.v[v] = out[v];
-                        if (L.nt)
-                            store_nt16(&at_mut<Chunk<R, V>>(row, L.lane_b), o);
-                        else
-                            at_mut<Chunk<R, V>>(row, L.lane_b) = o;
+                for (int v = 0; v < V; ++v) o.v[v] = out[v];
+                if (L.st_all) {
+                    if (L.nt)
+                        store_nt16(&at_mut<Chunk<R, V>>(row, L.lane_b), o);
+                    else
+                        at_mut<Chunk<R, V>>(row, L.lane_b) = o;
+                } else if constexpr ((EK & 2) != 0) {
+                    // the lane holding the east ring column and interior
+                    // columns before it stores element by element
+                    if (L.st_part) {
+#pragma unroll
+                        for (int v = 0; v < V; ++v)
+                            if (L.st[v]) at_mut<R>(row, L.lane_b + v * (uint32_t)sizeof(R)) = out[v];
                     }
-                } else {
-#pragma unroll
-                    for (int v = 0; v < V; ++v)
-                        if (L.st[v]) at_mut<R>(row, L.lane_b + v * (uint32_t)sizeof(R)) = out[v];
                 }
             }
         }
-        m2_level<R, T, P, MODE, EDGE, RES, J, S + 1, G>(g, uout, gacc, L, m, r, sc, sr);
+        m2_level<R, T, P, MODE, EK, RES, J, S + 1, G>(g, uout, gacc, L, m, r, sc, sr);
     }
 }
 
-template <typename R, int T, int P, int MODE, bool EDGE, bool RES, int J, int G = -1>
+template <typename R, int T, int P, int MODE, int EK, bool RES, int J, int G = -1>
 __device__ __forceinline__ void m2_steps(const Geom &g, const R *__restrict__ uin,
                                          R *__restrict__ uout, const R *__restrict__ bsrc,
                                          double *__restrict__ gacc, const MLane &L, MRegs<R, T, P> &m, const int base, Cur &lc,
@@ -409,7 +423,7 @@ __device__ __forceinline__ void m2_steps(const Geom &g, const R *__restrict__ ui
         // registers) and r+1-RA (accumulator, P = 1) held; at the last P
         // steps this reads rows no level uses, which keeps the loads
         // unconditional
-        m2_load<R, T, P, MODE, EDGE, (J + P) % M::LR, (J + P) % M::BQ, (J + 1) % M::RA>(
+        m2_load<R, T, P, MODE, EK, (J + P) % M::LR, (J + P) % M::BQ, (J + 1) % M::RA>(
             g, uin, bsrc, gacc, L, m, lc);
         if constexpr (!M::WRITE_FIRST) to_lds();
         if constexpr (MODE == MODE_ADJOINT) {
@@ -417,22 +431,22 @@ __device__ __forceinline__ void m2_steps(const Geom &g, const R *__restrict__ ui
             R v0[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) v0[v] = m.l0[J % M::LR][v];
-            m2_accumulate<R, T, P, MODE, EDGE, J % M::RA, T == 1>(g, gacc, L, m, r, v0);
+            m2_accumulate<R, T, P, MODE, EK, J % M::RA, T == 1>(g, gacc, L, m, r, v0);
         }
         // level 1's source row was read by the last level of the step before;
         // a step that computes no level reads the next step's row itself
         if constexpr (MODE == MODE_POISSON && m2_lmax<T, M::U, G, J>() == 0 &&
                       m2_next_l1<T, M::U, G, J>())
             m2_read_src<R, T, P, 1, 0>(L, m, sr);
-        m2_level<R, T, P, MODE, EDGE, RES, J, 1, G>(g, uout, gacc, L, m, r, sc, sr);
+        m2_level<R, T, P, MODE, EK, RES, J, 1, G>(g, uout, gacc, L, m, r, sc, sr);
         sc.advance(g);
         sr = sr + 1 == M::RB ? 0 : sr + 1;
-        m2_steps<R, T, P, MODE, EDGE, RES, J + 1, G>(g, uin, uout, bsrc, gacc, L, m, base, lc, sc,
+        m2_steps<R, T, P, MODE, EK, RES, J + 1, G>(g, uin, uout, bsrc, gacc, L, m, base, lc, sc,
                                                      sr);
     }
 }
 
-template <typename R, int T, int P, int MODE, bool EDGE, bool RES>
+template <typename R, int T, int P, int MODE, int EK, bool RES>
 __device__ __forceinline__ void m2_body(const Geom &g, const R *__restrict__ uin,
                                         R *__restrict__ uout, const R *__restrict__ bsrc,
                                         double *__restrict__ res_slot,
@@ -460,20 +474,20 @@ __device__ __forceinline__ void m2_body(const Geom &g, const R *__restrict__ uin
     lc.init(g, r0);
     sc.init(g, r0 - T);
     // rows r0 .. r0+P-1 -> slots 0 .. P-1
-    m2_load<R, T, P, MODE, EDGE, 0, 0, 0>(g, uin, bsrc, gacc, L, m, lc);
-    if constexpr (P > 1) m2_load<R, T, P, MODE, EDGE, 1, 1 % S::BQ, 1 % S::RA>(g, uin, bsrc, gacc, L, m, lc);
-    if constexpr (P > 2) m2_load<R, T, P, MODE, EDGE, 2, 2 % S::BQ, 2 % S::RA>(g, uin, bsrc, gacc, L, m, lc);
+    m2_load<R, T, P, MODE, EK, 0, 0, 0>(g, uin, bsrc, gacc, L, m, lc);
+    if constexpr (P > 1) m2_load<R, T, P, MODE, EK, 1, 1 % S::BQ, 1 % S::RA>(g, uin, bsrc, gacc, L, m, lc);
+    if constexpr (P > 2) m2_load<R, T, P, MODE, EK, 2, 2 % S::BQ, 2 % S::RA>(g, uin, bsrc, gacc, L, m, lc);
     int sr = 0;  // LDS source slot of the current row
     int base = r0;
     if constexpr (MODE != MODE_ADJOINT && T > 1) {
         // the tile's first group (and, from depth 7 on, its second) skip the
         // levels still outside the output's dependence cone (the adjoint
         // pass accumulates every level it holds, so it runs them all)
-        m2_steps<R, T, P, MODE, EDGE, RES, 0, 0>(g, uin, uout, bsrc, gacc, L, m, base, lc, sc, sr);
+        m2_steps<R, T, P, MODE, EK, RES, 0, 0>(g, uin, uout, bsrc, gacc, L, m, base, lc, sc, sr);
         base += S::U;
         if constexpr (T > S::U / 2) {
             if (base <= L.r1) {
-                m2_steps<R, T, P, MODE, EDGE, RES, 0, 1>(g, uin, uout, bsrc, gacc, L, m, base, lc,
+                m2_steps<R, T, P, MODE, EK, RES, 0, 1>(g, uin, uout, bsrc, gacc, L, m, base, lc,
                                                          sc, sr);
                 base += S::U;
             }
@@ -483,7 +497,7 @@ __device__ __forceinline__ void m2_body(const Geom &g, const R *__restrict__ uin
     // lies before the tile and is not an output)
     if constexpr (MODE == MODE_POISSON && T == 1) m2_read_src<R, T, P, 1>(L, m, sr);
     for (; base <= L.r1; base += S::U)
-        m2_steps<R, T, P, MODE, EDGE, RES, 0>(g, uin, uout, bsrc, gacc, L, m, base, lc, sc, sr);
+        m2_steps<R, T, P, MODE, EK, RES, 0>(g, uin, uout, bsrc, gacc, L, m, base, lc, sc, sr);
     if constexpr (RES) {
         const double a = wave_sum(m.acc);
         if ((threadIdx.x & 63) == 0) *res_slot = a;
@@ -515,41 +529,56 @@ __device__ __forceinline__ void m2_run(const Geom &g, const R *__restrict__ uin,
     L.r1 = L.oy1 - 1 + T;
     const int c = a + lane * V;
     L.c = c;
-    L.ld = c >= -V && c <= nx;
+    // lanes whose chunk lies beyond the ring read column 0's chunk instead
+    const bool ld = c >= -V && c <= nx;
     {
         int bx, lx;
-        owner(L.ld ? c : 0, g.e[0], g.nb[0], bx, lx);
+        owner(ld ? c : 0, g.e[0], g.nb[0], bx, lx);
         L.lane_b = (uint32_t)(((int64_t)bx * g.bstride + g.ax + lx) * (int64_t)sizeof(R));
-        L.ldb = SRC && c >= 0 && c < nx;
-        L.src_b = (uint32_t)(((int64_t)bx * g.sstride + (L.ldb ? lx : 0)) * (int64_t)sizeof(R));
+        const bool ldb = SRC && c >= 0 && c < nx;
+        L.src_b = (uint32_t)(((int64_t)bx * g.sstride + (ldb ? lx : 0)) * (int64_t)sizeof(R));
     }
     {
         // lanes 0 and 63 fetch the cells just outside the strip; the others
         // re-read their own first cell (a harmless in-bounds load)
         const int xe = lane == 0 ? a - 1 : lane == 63 ? a + S::W : c;
-        L.lde = xe >= -1 && xe <= nx && (lane == 0 || lane == 63 || L.ld);
+        const bool lde = xe >= -1 && xe <= nx && (lane == 0 || lane == 63 || ld);
         int bx, lx;
-        owner(L.lde ? xe : 0, g.e[0], g.nb[0], bx, lx);
+        owner(lde ? xe : 0, g.e[0], g.nb[0], bx, lx);
         L.edge_b = (uint32_t)(((int64_t)bx * g.bstride + g.ax + lx) * (int64_t)sizeof(R));
     }
     L.out_lane = lane >= S::L0 && lane < S::L1;
     L.nt = nt;
+    bool all = L.out_lane, any = false;
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
         const int x = c + v;
         L.upd[v] = x >= 0 && x < nx;
         L.st[v] = v < V && L.upd[v] && L.out_lane;
+        if (v < V) {
+            all = all && L.upd[v];
+            any = any || L.st[v];
+        }
     }
+    L.st_all = all;
+    L.st_part = any && !all;
     // rows r0 .. r1 + P are read; an interior tile reads only grid rows and
     // columns, none of them on the ring
     static_assert(MODE != MODE_ADJOINT || P == 1, "the adjoint pass prefetches one row");
     static_assert(MODE != MODE_ADJOINT || T + 1 <= S::RA, "adjoint accumulator ring too small");
+    // edge kinds: bit 0 = the tile reads rows on or beyond the ring (row
+    // tests), bit 1 = the strip holds columns on or beyond it (column tests)
     const int r0 = L.oy0 - T;
-    const bool edge = a < 0 || a + S::W > nx || r0 < 0 || L.r1 + P > ny - 1;
-    if (edge)
-        m2_body<R, T, P, MODE, true, RES>(g, uin, uout, bsrc, res_slot, gacc, L, r0);
+    const bool ex = a < 0 || a + S::W > nx;
+    const bool ey = r0 < 0 || L.r1 + P > ny - 1;
+    // (the middle tiles of the outer strips run the copy with both tests: a
+    // fourth copy pushes the kernel past the registers of two waves per SIMD)
+    if (ex)
+        m2_body<R, T, P, MODE, 3, RES>(g, uin, uout, bsrc, res_slot, gacc, L, r0);
+    else if (ey)
+        m2_body<R, T, P, MODE, 1, RES>(g, uin, uout, bsrc, res_slot, gacc, L, r0);
     else
-        m2_body<R, T, P, MODE, false, RES>(g, uin, uout, bsrc, res_slot, gacc, L, r0);
+        m2_body<R, T, P, MODE, 0, RES>(g, uin, uout, bsrc, res_slot, gacc, L, r0);
 }
 
 // uout may be NULL (no stores: residual only); res (used when RES) receives
