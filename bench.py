@@ -828,10 +828,10 @@ def main():
     if flags & jb.JACOBI_FLAG_EXPLICIT_HALO:
         kname = "k_sweep_tile<float, true>"
     else:
-        # Poisson pass kernel of depth d_dom and its prefetch distance; the
-        # traffic record aggregates its two residual variants
-        kname = "k_march2d<float, %d, %d, 1>" % (
-            d_dom, 3 if flags & jb.JACOBI_FLAG_DEEP_PREFETCH else 1)
+        # Poisson pass kernel of depth d_dom and its prefetch distance (two
+        # rows ahead up to depth 13); the traffic record aggregates its two
+        # residual variants
+        kname = "k_march2d<float, %d, %d, 1>" % (d_dom, 2 if d_dom <= 13 else 1)
     traffic = traffic_for(kname)
     hbm_frac = hbm_gbs / HBM_PEAK_GBS
     alu_frac = alu_tops / ALU_PEAK_TOPS
@@ -877,7 +877,7 @@ def main():
             "check_every": CHECK_EVERY, "schedule": schedule, "t_depth": depth, "rows": rows,
             "explicit_halo": bool(flags & jb.JACOBI_FLAG_EXPLICIT_HALO),
             "nt_stores": bool(flags & jb.JACOBI_FLAG_NT_STORES),
-            "deep_prefetch": bool(flags & jb.JACOBI_FLAG_DEEP_PREFETCH), "flags": flags,
+            "flags": flags,
             "parallelism": "single GPU",
         },
         "roofline": roof,

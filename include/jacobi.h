@@ -71,9 +71,9 @@ enum jacobi_flags {
     /* Store pass outputs with the non-temporal hint (not kept in the caches).
      * A pure performance choice; results are identical either way. */
     JACOBI_FLAG_NT_STORES = 2,
-    /* 2D passes load rows three steps ahead of their use instead of one
-     * (more bytes in flight per wave, more registers per wave).  A pure
-     * performance choice; results are identical either way. */
+    /* Accepted and ignored: the 2D passes now choose how far ahead they load
+     * by their depth (two rows at depths up to 13, one row beyond and in the
+     * adjoint pass).  Kept so that callers that set it keep working. */
     JACOBI_FLAG_DEEP_PREFETCH = 4,
     /* With JACOBI_FLAG_EXPLICIT_HALO (required): cut the blocks into up to 4
      * slabs of block layers along the slowest axis and overlap each slab's

@@ -350,15 +350,15 @@ int check_handle(jacobi_t h) {
 // Tile height that makes one march launch fill the GPU in `rounds` whole
 // rounds of resident waves: the smallest height whose tiles (edge bands and
 // outer strips included) number at most rounds x (waves per CU x CUs).
-int balanced_rows(const jacobi_s *h, int depth, int mode, int rounds, int deep) {
+int balanced_rows(const jacobi_s *h, int depth, int mode, int rounds) {
     if (h->g.ndim != 2) return 64;
     int cus = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
         return 64;
-    const int wpc = h->dtype == JACOBI_F32 ? jac::march2d_waves_per_cu<float>(depth, mode, deep)
-                                           : jac::march2d_waves_per_cu<double>(depth, mode, deep);
+    const int wpc = h->dtype == JACOBI_F32 ? jac::march2d_waves_per_cu<float>(depth, mode)
+                                           : jac::march2d_waves_per_cu<double>(depth, mode);
     if (wpc <= 0) return 64;
     const int64_t slots = (int64_t)rounds * wpc * cus;
     auto tiles = [&](int rows) {
@@ -399,11 +399,10 @@ bool march_fits(const Geom &g, int dtype) {
     return span * es < 4294967296.0 - 4096.0;
 }
 
-int deep_of(const jacobi_s *h) { return (h->flags & JACOBI_FLAG_DEEP_PREFETCH) ? 1 : 0; }
 
 int default_rows(const jacobi_s *h) {
     const int d = h->depth > 0 ? h->depth : default_depth(h);
-    return balanced_rows(h, d, h->has_source ? 1 : 0, 1, deep_of(h));
+    return balanced_rows(h, d, h->has_source ? 1 : 0, 1);
 }
 
 int max_depth(int ndim, int dtype) {
@@ -474,12 +473,12 @@ int do_residual(jacobi_t h, double *out) {
     }
     if (h->g.ndim == 2 && march_fits(h->g, h->dtype)) {
         // one residual-only pass of the march kernel (no stores)
-        const int rows = balanced_rows(h, 1, h->has_source ? 1 : 0, 1, deep_of(h));
+        const int rows = balanced_rows(h, 1, h->has_source ? 1 : 0, 1);
         const int64_t nw = jac::march2d_work_items<R>(h->g, 1, rows);
         if (nw < 0 || (size_t)nw > h->lay.part_cap) return fail(JACOBI_E_INVAL, "partials overflow");
         int64_t nwork = 0;
         HIP_TRY(jac::launch_sweep2d_march<R>(h->g, h->u[h->cur], nullptr, b, h->partials, nullptr, 1, rows,
-                                             h->stream, &nwork, 0, deep_of(h)),
+                                             h->stream, &nwork, 0),
                 "residual launch");
         HIP_TRY(jac::launch_residual_final(h->partials, (int)nwork, out, h->stream),
                 "residual launch");
@@ -656,7 +655,7 @@ int do_sweep(jacobi_t h, int64_t n, double *res_first, bool sync_halos = true) {
         int64_t nwork = 0;
         HIP_TRY(jac::launch_sweep2d_march<R>(h->g, h->u[h->cur], h->u[h->cur ^ 1], b, part, nullptr, t,
                                              rows, h->stream, &nwork,
-                                             h->flags & JACOBI_FLAG_NT_STORES, deep_of(h)),
+                                             h->flags & JACOBI_FLAG_NT_STORES),
                 "sweep launch");
         rc = prof_end(h, t);
         if (rc) return rc;
@@ -733,7 +732,7 @@ int deep_rows(jacobi_t h, int depth) {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
         return 64;
-    const int wpc = jac::march2d_waves_per_cu<R>(depth, h->has_source ? 1 : 0, 0);
+    const int wpc = jac::march2d_waves_per_cu<R>(depth, h->has_source ? 1 : 0);
     if (wpc <= 0) return 64;
     const int64_t slots = (int64_t)wpc * cus;
     std::vector<jac::BatchGrid> t((size_t)h->g.nblocks);
@@ -791,7 +790,7 @@ int do_deep_sweep(jacobi_t h, int64_t n, double *res_first, bool sync_halos) {
         const int *pre = h->d_prefix + (size_t)t * (nb + 1);
         if (nd == 2)
             HIP_TRY(jac::launch_march2d_batch<R>(h->d_tab[h->cur], pre, (int)nb, h->d_active, h->d_pc,
-                                                 nullptr, true, t, rows, nwork, h->stream, 0,
+                                                 nullptr, true, t, rows, nwork, h->stream,
                                                  h->has_source ? 1 : 0),
                     "deep pass launch");
         else
@@ -815,7 +814,7 @@ int do_adjoint(jacobi_t h, int64_t n) {
     // 820 GLUP/s vs 586 at depth 4; depth 8 runs out of registers for the
     // FP64 accumulator ring)
     int depth = h->adj_depth > 0 ? h->adj_depth : (h->dtype == JACOBI_F32 ? 7 : 3);
-    const int rows = h->adj_rows > 0 ? h->adj_rows : balanced_rows(h, depth, 2, 1, 0);
+    const int rows = h->adj_rows > 0 ? h->adj_rows : balanced_rows(h, depth, 2, 1);
     int64_t left = n;
     while (left > 0) {
         const int64_t passes = (left + depth - 1) / depth;
@@ -1421,21 +1420,19 @@ int jacobi_autotune(jacobi_t h, int64_t n_sweeps, int with_source, int *t_depth,
             const int *list;
             const int nd = jac::march2d_depths(h->dtype, &list);
             static const int kRows[] = {16, 32, 64, 96, 128, 192, 256};
-            for (int i = 0; i < nd; ++i)
-                for (int deep = 0; deep <= 1; ++deep) {
-                    std::vector<int> rs(kRows, kRows + sizeof(kRows) / sizeof(int));
-                    for (int k = 1; k <= 3; ++k) rs.push_back(balanced_rows(h, list[i], src, k, deep));
-                    std::vector<int> seen;
-                    const int fd = deep ? (int)JACOBI_FLAG_DEEP_PREFETCH : 0;
-                    for (int r : rs) {
-                        bool dup = false;
-                        for (int q : seen) dup = dup || q == r;
-                        if (dup) continue;
-                        seen.push_back(r);
-                        cands.push_back({list[i], r, fd});
-                        cands.push_back({list[i], r, fd | (int)JACOBI_FLAG_NT_STORES});
-                    }
+            for (int i = 0; i < nd; ++i) {
+                std::vector<int> rs(kRows, kRows + sizeof(kRows) / sizeof(int));
+                for (int k = 1; k <= 3; ++k) rs.push_back(balanced_rows(h, list[i], src, k));
+                std::vector<int> seen;
+                for (int r : rs) {
+                    bool dup = false;
+                    for (int q : seen) dup = dup || q == r;
+                    if (dup) continue;
+                    seen.push_back(r);
+                    cands.push_back({list[i], r, 0});
+                    cands.push_back({list[i], r, (int)JACOBI_FLAG_NT_STORES});
                 }
+            }
         }
         const bool saved_src = h->has_source;
         const bool saved_prof = h->profiling;

@@ -17,8 +17,8 @@
 // strip arrive by one scalar load per row.  Level T is the pass's output.
 // A strip recomputes T - 1 columns on each side and a segment T rows on each
 // side; only the strip's output lanes [L0, L1) and the segment's own rows
-// are stored.  Rows are loaded P steps ahead of use (P = 1, or 3 with the
-// deep-prefetch option), straight into their ring slot, so no register
+// are stored.  Rows are loaded P steps ahead of use (P = 2 at most depths,
+// see m2_pf), straight into their ring slot, so no register
 // copies are needed.  A source row waits in
 // registers for one step before it is written to the wave's LDS ring (it is
 // first read one step after that), so the wait for its load overlaps a whole
@@ -649,17 +649,25 @@ static int64_t m2_nwork(const Geom &g, int rows) {
     return m2_tiles(g.n[0], g.n[1], S::OW, rows, T).nwork;
 }
 
-// deep != 0: the kernels that load three rows ahead (otherwise one)
+// Prefetch distance of the Laplace and Poisson passes of depth T: two rows
+// ahead (one step of arithmetic did not always cover the memory latency;
+// measured at 8192^2 FP32, depth 13: 0.239 -> 0.222 ms per pass, depth 8:
+// -3%, depth 4: equal), except at the depths whose levels leave no registers
+// for the two extra rows (14 and 16).  The adjoint pass loads one row ahead.
+template <int T>
+constexpr int m2_pf() {
+    return T <= 13 ? 2 : 1;
+}
+
 template <typename R, int T>
 hipError_t m2_launch_t(const Geom &g, const void *uin, void *uout, const void *b, double *res,
-                       double *gacc, int rows, hipStream_t st, int64_t *nwork_out, int nt,
-                       int deep);
+                       double *gacc, int rows, hipStream_t st, int64_t *nwork_out, int nt);
 template <typename R, int T>
 hipError_t m2b_launch_t(const BatchGrid *grids, const int *prefix, int ngrids, const int *active,
                         const int *pass_count, double *res, bool store, int rows, int nwork,
-                        hipStream_t st, int deep, int mode);
+                        hipStream_t st, int mode);
 template <typename R, int T>
-int m2_waves_per_cu_t(int mode, int deep);
+int m2_waves_per_cu_t(int mode);
 
 #ifdef JAC_MARCH2D_DEPTH
 
@@ -701,14 +709,11 @@ static hipError_t m2_launch_p(const Geom &g, const void *uin, void *uout, const 
 
 template <typename R, int T>
 hipError_t m2_launch_t(const Geom &g, const void *uin, void *uout, const void *b, double *res,
-                       double *gacc, int rows, hipStream_t st, int64_t *nwork_out, int nt,
-                       int deep) {
+                       double *gacc, int rows, hipStream_t st, int64_t *nwork_out, int nt) {
     const int64_t nwork = m2_nwork<R, T>(g, rows);
     if (nwork_out) *nwork_out = nwork;
     if (nwork > 0x7fffffff - 3) return hipErrorInvalidValue;
-    if (deep && !gacc)
-        return m2_launch_p<R, T, 3>(g, uin, uout, b, res, gacc, rows, (int)nwork, st, nt);
-    return m2_launch_p<R, T, 1>(g, uin, uout, b, res, gacc, rows, (int)nwork, st, nt);
+    return m2_launch_p<R, T, m2_pf<T>()>(g, uin, uout, b, res, gacc, rows, (int)nwork, st, nt);
 }
 
 template <typename R, int T, int P>
@@ -717,8 +722,8 @@ static hipError_t m2b_launch_p(const BatchGrid *grids, const int *prefix, int ng
                                int rows, int nwork, hipStream_t st, int mode) {
     const int grid = (nwork + 3) / 4;
     if (mode == MODE_LAPLACE) {
-        // the deep-halo form without a source: no residual, one-row prefetch
-        if (res || P != 1) return hipErrorInvalidValue;
+        // the deep-halo form without a source: no residual
+        if (res) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_march2d_batch<R, T, P, false, MODE_LAPLACE>), dim3(grid), dim3(256),
                            0, st, grids, prefix, ngrids, active, pass_count, res, store ? 1 : 0,
                            rows, nwork);
@@ -736,16 +741,14 @@ static hipError_t m2b_launch_p(const BatchGrid *grids, const int *prefix, int ng
 template <typename R, int T>
 hipError_t m2b_launch_t(const BatchGrid *grids, const int *prefix, int ngrids, const int *active,
                         const int *pass_count, double *res, bool store, int rows, int nwork,
-                        hipStream_t st, int deep, int mode) {
-    if (deep)
-        return m2b_launch_p<R, T, 3>(grids, prefix, ngrids, active, pass_count, res, store, rows,
-                                     nwork, st, mode);
-    return m2b_launch_p<R, T, 1>(grids, prefix, ngrids, active, pass_count, res, store, rows,
-                                 nwork, st, mode);
+                        hipStream_t st, int mode) {
+    return m2b_launch_p<R, T, m2_pf<T>()>(grids, prefix, ngrids, active, pass_count, res, store,
+                                          rows, nwork, st, mode);
 }
 
 template <typename R, int T>
-int m2_waves_per_cu_t(int mode, int deep) {
+int m2_waves_per_cu_t(int mode) {
+    constexpr int P = m2_pf<T>();
     int blocks = 0;
     hipError_t e;
     if (mode == MODE_ADJOINT) {
@@ -753,25 +756,21 @@ int m2_waves_per_cu_t(int mode, int deep) {
             return 0;
         else
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 1, MODE_ADJOINT, false>, 256, 0);
-    } else if (mode == MODE_POISSON && deep)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 3, MODE_POISSON, false>, 256, 0);
-    else if (mode == MODE_POISSON)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 1, MODE_POISSON, false>, 256, 0);
-    else if (deep)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 3, MODE_LAPLACE, false>, 256, 0);
+    } else if (mode == MODE_POISSON)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, P, MODE_POISSON, false>, 256, 0);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 1, MODE_LAPLACE, false>, 256, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, P, MODE_LAPLACE, false>, 256, 0);
     return e == hipSuccess ? blocks * 4 : 0;
 }
 
 #define JAC_M2_INSTANTIATE(R, T)                                                              \
     template hipError_t m2_launch_t<R, T>(const Geom &, const void *, void *, const void *,    \
                                           double *, double *, int, hipStream_t, int64_t *,     \
-                                          int, int);                                           \
+                                          int);                                                \
     template hipError_t m2b_launch_t<R, T>(const BatchGrid *, const int *, int, const int *,   \
                                            const int *, double *, bool, int, int,              \
-                                           hipStream_t, int, int);                             \
-    template int m2_waves_per_cu_t<R, T>(int, int);
+                                           hipStream_t, int);                                  \
+    template int m2_waves_per_cu_t<R, T>(int);
 
 JAC_M2_INSTANTIATE(float, JAC_MARCH2D_DEPTH)
 #if JAC_MARCH2D_DEPTH <= 4
@@ -821,8 +820,8 @@ int march2d_depths(int dtype, const int **list) {
     }
 
 template <typename R>
-int march2d_waves_per_cu(int depth, int mode, int deep) {
-    JAC_M2_SWITCH(depth, m2_waves_per_cu_t, R, 0, mode, deep)
+int march2d_waves_per_cu(int depth, int mode) {
+    JAC_M2_SWITCH(depth, m2_waves_per_cu_t, R, 0, mode)
 }
 
 template <typename R>
@@ -834,9 +833,9 @@ int64_t march2d_work_items(const Geom &g, int depth, int rows) {
 template <typename R>
 hipError_t launch_sweep2d_march(const Geom &g, const void *uin, void *uout, const void *b,
                                 double *res, double *gacc, int depth, int rows, hipStream_t st,
-                                int64_t *nwork, int nt, int deep) {
+                                int64_t *nwork, int nt) {
     JAC_M2_SWITCH(depth, m2_launch_t, R, hipErrorInvalidValue, g, uin, uout, b, res, gacc, rows,
-                  st, nwork, nt, deep)
+                  st, nwork, nt)
 }
 
 template <typename R>
@@ -847,31 +846,30 @@ int64_t march2d_batch_work(const Geom &g, int depth, int rows) {
 template <typename R>
 hipError_t launch_march2d_batch(const BatchGrid *grids, const int *prefix, int ngrids,
                                 const int *active, const int *pass_count, double *res, bool store,
-                                int depth, int rows, int nwork, hipStream_t st, int deep,
-                                int mode) {
+                                int depth, int rows, int nwork, hipStream_t st, int mode) {
     if (nwork <= 0) return hipSuccess;
     JAC_M2_SWITCH(depth, m2b_launch_t, R, hipErrorInvalidValue, grids, prefix, ngrids, active,
-                  pass_count, res, store, rows, nwork, st, deep, mode)
+                  pass_count, res, store, rows, nwork, st, mode)
 }
 
 template hipError_t launch_sweep2d_march<float>(const Geom &, const void *, void *, const void *,
                                                 double *, double *, int, int, hipStream_t,
-                                                int64_t *, int, int);
+                                                int64_t *, int);
 template hipError_t launch_sweep2d_march<double>(const Geom &, const void *, void *, const void *,
                                                  double *, double *, int, int, hipStream_t,
-                                                 int64_t *, int, int);
+                                                 int64_t *, int);
 template int64_t march2d_batch_work<float>(const Geom &, int, int);
 template int64_t march2d_batch_work<double>(const Geom &, int, int);
 template hipError_t launch_march2d_batch<float>(const BatchGrid *, const int *, int, const int *,
                                                 const int *, double *, bool, int, int, int,
-                                                hipStream_t, int, int);
+                                                hipStream_t, int);
 template hipError_t launch_march2d_batch<double>(const BatchGrid *, const int *, int, const int *,
                                                  const int *, double *, bool, int, int, int,
-                                                 hipStream_t, int, int);
+                                                 hipStream_t, int);
 template int64_t march2d_work_items<float>(const Geom &, int, int);
 template int64_t march2d_work_items<double>(const Geom &, int, int);
-template int march2d_waves_per_cu<float>(int, int, int);
-template int march2d_waves_per_cu<double>(int, int, int);
+template int march2d_waves_per_cu<float>(int, int);
+template int march2d_waves_per_cu<double>(int, int);
 
 #endif  // JAC_MARCH2D_DEPTH
 

@@ -63,15 +63,14 @@ hipError_t launch_halo_send(const Geom &g, void *s, int64_t b0, int64_t b1, hipS
 template <typename R>
 hipError_t launch_sweep2d_march(const Geom &g, const void *uin, void *uout, const void *b,
                                 double *res, double *gacc, int depth, int rows, hipStream_t st,
-                                int64_t *nwork, int nt = 0, int deep = 0);
+                                int64_t *nwork, int nt = 0);
 // Work items (waves) of one march launch; -1 for an unknown depth.
 template <typename R>
 int64_t march2d_work_items(const Geom &g, int depth, int rows);
 // Resident waves per CU of the depth-`depth` march kernel in `mode`
-// (0 Laplace, 1 Poisson, 2 adjoint; deep: the three-rows-ahead kernel); 0 if
-// unknown.
+// (0 Laplace, 1 Poisson, 2 adjoint); 0 if unknown.
 template <typename R>
-int march2d_waves_per_cu(int depth, int mode, int deep = 0);
+int march2d_waves_per_cu(int depth, int mode);
 // Depths compiled for the 2D march kernel, ascending; returns the count.
 int march2d_depths(int dtype, const int **list);
 
@@ -79,12 +78,11 @@ int march2d_depths(int dtype, const int **list);
 // Batched pass over the grids of a batch (Poisson kernels; see
 // k_march2d_batch).  nwork = prefix[ngrids]; res: one partial per work item
 // (NULL: no residual); store = false: residual only.
-// mode: 1 Poisson (the grids' sources), 0 Laplace (no residual, deep = 0).
+// mode: 1 Poisson (the grids' sources), 0 Laplace (no residual).
 template <typename R>
 hipError_t launch_march2d_batch(const BatchGrid *grids, const int *prefix, int ngrids,
                                 const int *active, const int *pass_count, double *res, bool store,
-                                int depth, int rows, int nwork, hipStream_t st, int deep = 0,
-                                int mode = 1);
+                                int depth, int rows, int nwork, hipStream_t st, int mode = 1);
 // Work items of one grid at this depth / tile height.
 template <typename R>
 int64_t march2d_batch_work(const Geom &g, int depth, int rows);

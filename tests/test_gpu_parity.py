@@ -72,13 +72,13 @@ def test_2d_bit_exact_all_depths(device, dtype, case):
     depths = list(range(1, jb.jacobi_max_depth(2, code) + 1))
     for depth in depths:
         for rows in (0, 8, 64):
-            for fl in (0, jb.JACOBI_FLAG_DEEP_PREFETCH):
+            for fl in (0, jb.JACOBI_FLAG_NT_STORES):
                 say("2d case=%s dtype=%s depth=%d rows=%d flags=%d"
                     % (case, np.dtype(dtype).name, depth, rows, fl))
                 got, _ = run_device(U0, f, h2, K, (bx, by), dtype, device, depth=depth, rows=rows,
                                     flags=fl)
                 assert_bits(got, want, "2d %s depth %d rows %d flags %d" % (case, depth, rows, fl))
-    for fl in (0, jb.JACOBI_FLAG_DEEP_PREFETCH):
+    for fl in (0, jb.JACOBI_FLAG_NT_STORES):
         got, _ = run_device(U0, None, h2, K, (bx, by), dtype, device, depth=depths[-1], flags=fl)
         assert_bits(got, want_l, "2d laplace %s flags %d" % (case, fl))
     for rg in (0, 1, 3, 5, 64):
@@ -141,7 +141,8 @@ def test_2d_edge_band_tiling(device, case):
         np.testing.assert_allclose(res, ores, rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("flags", [0, 4])
+# 6: non-temporal stores, and the prefetch flag (accepted, no effect)
+@pytest.mark.parametrize("flags", [0, 6])
 @pytest.mark.parametrize("case", [(37, 29, 3, 4, 13), (513, 260, 3, 5, 25), (1, 1, 1, 1, 3)])
 def test_2d_residuals_and_states(device, case, flags):
     """solve() with a residual every 4 sweeps (the residual folded into the
