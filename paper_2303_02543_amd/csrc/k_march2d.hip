@@ -80,8 +80,10 @@ struct M2 {
 // heights follow from (h + 2T) = (rows + 2T) * F / 16, with F = kBand16 for
 // the bands and kOuter16 for the outer strips, so edge tiles take about as
 // long as interior ones and a pass, whose tiles all run as one generation
-// of waves, is not held up by its edges.
-constexpr int kBand16 = 14, kOuter16 = 12;
+// of waves, is not held up by its edges.  F was measured on MI355X (8192^2
+// FP32, depth 13): 15/13 0.232 ms per pass, 14/12 0.225, 13/11 0.215,
+// 12/10 0.215.
+constexpr int kBand16 = 13, kOuter16 = 11;
 struct M2Tiles {
     int ns, hb, ho, sa, sb, na, nb;  // strips, band / outer tile height, tiles per inner / outer strip, inner / outer strips
     int64_t ninner, nwork;           // tiles of the inner strips, all tiles

@@ -101,20 +101,20 @@ def test_2d_bit_exact_all_depths(device, dtype, case):
 
 # The 2D pass tiling: inner strips get an edge band of hb rows at the top and
 # the bottom and tiles of `rows` rows between, outer strips tiles of ho rows,
-# with h = max(min(rows, 8), (rows + 2T) * F // 16 - 2T), capped at ny, F = 14
-# for hb and 12 for ho.  Tiles of a strip that reaches the ring in x run the
+# with h = max(min(rows, 8), (rows + 2T) * F // 16 - 2T), capped at ny, F = 13
+# for hb and 11 for ho.  Tiles of a strip that reaches the ring in x run the
 # step with row and column tests, the other tiles that reach it in y the step
 # with row tests only.  FP32 strips hold 248 output columns at depth 4 and
 # 232 at depth 13.
 BAND_CASES = [
     # (nx, ny, bx, by, depth, rows): the tiling case it reaches
-    (700, 20, 3, 2, 4, 40),   # 3 strips; ny <= hb (34, capped at 20): one band per inner strip
+    (700, 20, 3, 2, 4, 40),   # 3 strips; ny <= hb (31, capped at 20): one band per inner strip
     (700, 40, 3, 4, 4, 40),   # hb < ny <= 2 hb: a top band and a bottom band only
-    (700, 149, 3, 4, 4, 40),  # bands of 34, middle tiles of 40, 40 and a 1-row tail
+    (700, 143, 3, 4, 4, 40),  # bands of 31, middle tiles of 40, 40 and a 1-row tail
     (100, 131, 2, 3, 4, 40),  # one strip: outer-strip tiles only
     (300, 131, 2, 3, 4, 40),  # two strips: outer-strip tiles only
     (700, 131, 3, 4, 13, 8),  # depth 13, hb and ho clamped to 8 rows
-    (1200, 300, 4, 3, 13, 60),  # six strips, hb = 49, ho = 38, ragged middle tile
+    (1200, 300, 4, 3, 13, 60),  # six strips, hb = 43, ho = 33, ragged middle tile
     (497, 131, 3, 4, 4, 40),  # the last strip 1 column wide: the inner strip reaches the ring in x
     (470, 131, 2, 3, 13, 40),  # the same at depth 13 (the last strip 6 columns wide)
 ]
