@@ -41,6 +41,12 @@
 
 namespace jac {
 
+// Waves per workgroup of the pass kernels.  The waves of a workgroup share
+// nothing (each has its own LDS ring); one wave per workgroup (a finished
+// wave freeing its slot at once) measured the same as four on the 8192^2
+// pass and the 64-grid batch.
+constexpr int kM2Waves = 4;
+
 // Pass modes: Laplace (no source), Poisson (source b), and the adjoint pass,
 // which sweeps a zero-ring Laplace state and adds w * (every level it holds)
 // into an FP64 accumulator.
@@ -587,7 +593,7 @@ __device__ __forceinline__ void m2_run(const Geom &g, const R *__restrict__ uin,
 // one residual partial per work item; gacc is the FP64 accumulator of the
 // adjoint pass (MODE_ADJOINT only).
 template <typename R, int T, int P, int MODE, bool RES>
-__global__ __launch_bounds__(256) void k_march2d(Geom g, const R *__restrict__ uin,
+__global__ __launch_bounds__(64 * kM2Waves) void k_march2d(Geom g, const R *__restrict__ uin,
                                                  R *__restrict__ uout,
                                                  const R *__restrict__ bsrc,
                                                  double *__restrict__ res,
@@ -596,7 +602,7 @@ __global__ __launch_bounds__(256) void k_march2d(Geom g, const R *__restrict__ u
     using S = M2<R, T, P>;
     constexpr bool SRC = MODE == MODE_POISSON;
     // per wave: a ring of RB source rows, one 16-byte chunk per lane each
-    __shared__ Chunk<R, S::V> bsm[SRC ? 4 * S::RB * 64 : 1];
+    __shared__ Chunk<R, S::V> bsm[SRC ? kM2Waves * S::RB * 64 : 1];
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int wid = __builtin_amdgcn_readfirstlane(lb * (blockDim.x >> 6) + (threadIdx.x >> 6));
     if (wid >= nwork) return;
@@ -611,7 +617,7 @@ __global__ __launch_bounds__(256) void k_march2d(Geom g, const R *__restrict__ u
 // MODE: Poisson (the batched solver; the deep-halo form with a source) or
 // Laplace (the deep-halo form without one).
 template <typename R, int T, int P, bool RES, int MODE>
-__global__ __launch_bounds__(256) void k_march2d_batch(const BatchGrid *__restrict__ grids,
+__global__ __launch_bounds__(64 * kM2Waves) void k_march2d_batch(const BatchGrid *__restrict__ grids,
                                                        const int *__restrict__ prefix, int ngrids,
                                                        const int *__restrict__ active,
                                                        const int *__restrict__ pass_count,
@@ -619,7 +625,7 @@ __global__ __launch_bounds__(256) void k_march2d_batch(const BatchGrid *__restri
                                                        int rows, int nwork) {
     using S = M2<R, T, P>;
     constexpr bool SRC = MODE == MODE_POISSON;
-    __shared__ Chunk<R, S::V> bsm[SRC ? 4 * S::RB * 64 : 1];
+    __shared__ Chunk<R, S::V> bsm[SRC ? kM2Waves * S::RB * 64 : 1];
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int wid = __builtin_amdgcn_readfirstlane(lb * (blockDim.x >> 6) + (threadIdx.x >> 6));
     if (wid >= nwork) return;
@@ -677,33 +683,33 @@ template <typename R, int T, int P>
 static hipError_t m2_launch_p(const Geom &g, const void *uin, void *uout, const void *b,
                               double *res, double *gacc, int rows, int nwork, hipStream_t st,
                               int nt) {
-    const int grid = (nwork + 3) / 4;
+    const int grid = (nwork + kM2Waves - 1) / kM2Waves;
     const R *bb = (const R *)b;
     if (gacc) {
         // adjoint passes go to depth 8 (the accumulator ring holds T + 1 rows)
         if constexpr (T > 8) {
             return hipErrorInvalidValue;
         } else {
-            hipLaunchKernelGGL((k_march2d<R, T, 1, MODE_ADJOINT, false>), dim3(grid), dim3(256), 0,
+            hipLaunchKernelGGL((k_march2d<R, T, 1, MODE_ADJOINT, false>), dim3(grid), dim3(64 * kM2Waves), 0,
                                st, g, (const R *)uin, (R *)uout, (const R *)nullptr,
                                (double *)nullptr, gacc, rows, nwork, nt);
             return hipGetLastError();
         }
     }
     if (b && res)
-        hipLaunchKernelGGL((k_march2d<R, T, P, MODE_POISSON, true>), dim3(grid), dim3(256), 0, st,
+        hipLaunchKernelGGL((k_march2d<R, T, P, MODE_POISSON, true>), dim3(grid), dim3(64 * kM2Waves), 0, st,
                            g, (const R *)uin, (R *)uout, bb, res, (double *)nullptr, rows, nwork,
                            nt);
     else if (b)
-        hipLaunchKernelGGL((k_march2d<R, T, P, MODE_POISSON, false>), dim3(grid), dim3(256), 0, st,
+        hipLaunchKernelGGL((k_march2d<R, T, P, MODE_POISSON, false>), dim3(grid), dim3(64 * kM2Waves), 0, st,
                            g, (const R *)uin, (R *)uout, bb, (double *)nullptr, (double *)nullptr,
                            rows, nwork, nt);
     else if (res)
-        hipLaunchKernelGGL((k_march2d<R, T, P, MODE_LAPLACE, true>), dim3(grid), dim3(256), 0, st,
+        hipLaunchKernelGGL((k_march2d<R, T, P, MODE_LAPLACE, true>), dim3(grid), dim3(64 * kM2Waves), 0, st,
                            g, (const R *)uin, (R *)uout, (const R *)nullptr, res,
                            (double *)nullptr, rows, nwork, nt);
     else
-        hipLaunchKernelGGL((k_march2d<R, T, P, MODE_LAPLACE, false>), dim3(grid), dim3(256), 0, st,
+        hipLaunchKernelGGL((k_march2d<R, T, P, MODE_LAPLACE, false>), dim3(grid), dim3(64 * kM2Waves), 0, st,
                            g, (const R *)uin, (R *)uout, (const R *)nullptr, (double *)nullptr,
                            (double *)nullptr, rows, nwork, nt);
     return hipGetLastError();
@@ -722,19 +728,19 @@ template <typename R, int T, int P>
 static hipError_t m2b_launch_p(const BatchGrid *grids, const int *prefix, int ngrids,
                                const int *active, const int *pass_count, double *res, bool store,
                                int rows, int nwork, hipStream_t st, int mode) {
-    const int grid = (nwork + 3) / 4;
+    const int grid = (nwork + kM2Waves - 1) / kM2Waves;
     if (mode == MODE_LAPLACE) {
         // the deep-halo form without a source: no residual
         if (res) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_march2d_batch<R, T, P, false, MODE_LAPLACE>), dim3(grid), dim3(256),
+        hipLaunchKernelGGL((k_march2d_batch<R, T, P, false, MODE_LAPLACE>), dim3(grid), dim3(64 * kM2Waves),
                            0, st, grids, prefix, ngrids, active, pass_count, res, store ? 1 : 0,
                            rows, nwork);
     } else if (res)
-        hipLaunchKernelGGL((k_march2d_batch<R, T, P, true, MODE_POISSON>), dim3(grid), dim3(256),
+        hipLaunchKernelGGL((k_march2d_batch<R, T, P, true, MODE_POISSON>), dim3(grid), dim3(64 * kM2Waves),
                            0, st, grids, prefix, ngrids, active, pass_count, res, store ? 1 : 0,
                            rows, nwork);
     else
-        hipLaunchKernelGGL((k_march2d_batch<R, T, P, false, MODE_POISSON>), dim3(grid), dim3(256),
+        hipLaunchKernelGGL((k_march2d_batch<R, T, P, false, MODE_POISSON>), dim3(grid), dim3(64 * kM2Waves),
                            0, st, grids, prefix, ngrids, active, pass_count, res, store ? 1 : 0,
                            rows, nwork);
     return hipGetLastError();
@@ -757,12 +763,12 @@ int m2_waves_per_cu_t(int mode) {
         if constexpr (T > 8)
             return 0;
         else
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 1, MODE_ADJOINT, false>, 256, 0);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, 1, MODE_ADJOINT, false>, 64 * kM2Waves, 0);
     } else if (mode == MODE_POISSON)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, P, MODE_POISSON, false>, 256, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, P, MODE_POISSON, false>, 64 * kM2Waves, 0);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, P, MODE_LAPLACE, false>, 256, 0);
-    return e == hipSuccess ? blocks * 4 : 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_march2d<R, T, P, MODE_LAPLACE, false>, 64 * kM2Waves, 0);
+    return e == hipSuccess ? blocks * kM2Waves : 0;
 }
 
 #define JAC_M2_INSTANTIATE(R, T)                                                              \
