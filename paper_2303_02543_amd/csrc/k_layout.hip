@@ -14,40 +14,72 @@
 
 namespace jac {
 
-// One thread per node of the full (n+2)^d array: the node's value goes to the
-// block that owns it (ring nodes to the domain-edge halo slots), in both state
-// buffers.  Internal halos are filled afterwards by the halo exchange.
+// The element maps below run over rows of the full array (or of the source
+// for k_scale_source): one workgroup per row (rows strided over the grid),
+// its threads walking the row block by block, so no element needs a
+// division to find its owner and every access is coalesced.  (A flat
+// grid-stride form, which split a 64-bit element index per element, ran at
+// ~2 TB/s; one element per thread with one workgroup per 256 columns was
+// slower still, bound by workgroup dispatch.)
+
+// Element offset of row y / plane z (ring-extended) in block (0, by, bz) at
+// local x = 0, and whether the row is on the Dirichlet ring (uniform).
+struct RowYZ {
+    int64_t base;
+    bool ring;
+};
+__device__ __forceinline__ RowYZ row_yz(const Geom &g, int y, int z) {
+    int by, ly, bz = 0, lz = 0;
+    owner(y, g.e[1], g.nb[1], by, ly);
+    if (g.ndim == 3) owner(z, g.e[2], g.nb[2], bz, lz);
+    RowYZ r;
+    r.base = local_offset(g, ((int64_t)bz * g.nb[1] + by) * g.nb[0], 0, ly, lz);
+    r.ring = y < 0 || y >= g.n[1] || (g.ndim == 3 && (z < 0 || z >= g.n[2]));
+    return r;
+}
+
+// Every node of the full (n+2)^d array goes to the block that owns it (ring
+// nodes to the domain-edge halo slots), in both state buffers.  Internal
+// halos are filled afterwards by the halo exchange.
 template <typename R>
 __global__ __launch_bounds__(256) void k_scatter(Geom g, const R *__restrict__ u,
                                                  R *__restrict__ s0, R *__restrict__ s1,
-                                                 int64_t total, int zero_ring) {
-    const int64_t nx2 = g.n[0] + 2, ny2 = g.n[1] + 2;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(i % nx2) - 1;
-        const int64_t rest = i / nx2;
-        const int y = (int)(rest % ny2) - 1;
-        const int z = (int)(rest / ny2) - 1;
-        const int64_t off = state_offset(g, x, y, z);
-        const bool ring = x < 0 || x >= g.n[0] || y < 0 || y >= g.n[1] ||
-                          (g.ndim == 3 && (z < 0 || z >= g.n[2]));
-        const R v = (zero_ring && ring) ? (R)0 : u[i];
-        s0[off] = v;
-        s1[off] = v;
+                                                 int64_t rows, int zero_ring) {
+    const int nx2 = g.n[0] + 2, ny2 = g.n[1] + 2;
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const RowYZ yz = row_yz(g, (int)(r % ny2) - 1, (int)(r / ny2) - 1);
+        const R *urow = u + r * nx2 + 1;  // urow[x], x in [-1, n]
+        for (int bx = 0; bx < g.nb[0]; ++bx) {
+            const int ext = extent(g.n[0], g.e[0], bx);
+            const int lo = bx == 0 ? -1 : 0, hi = bx == g.nb[0] - 1 ? ext + 1 : ext;
+            const int x0 = bx * g.e[0];
+            const int64_t boff = yz.base + (int64_t)bx * g.bstride;
+            for (int lx = lo + (int)threadIdx.x; lx < hi; lx += blockDim.x) {
+                const int x = x0 + lx;
+                const bool ring = yz.ring || x < 0 || x >= g.n[0];
+                const R v = (zero_ring && ring) ? (R)0 : urow[x];
+                s0[boff + lx] = v;
+                s1[boff + lx] = v;
+            }
+        }
     }
 }
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_gather(Geom g, const R *__restrict__ s,
-                                                R *__restrict__ u, int64_t total) {
-    const int64_t nx2 = g.n[0] + 2, ny2 = g.n[1] + 2;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(i % nx2) - 1;
-        const int64_t rest = i / nx2;
-        const int y = (int)(rest % ny2) - 1;
-        const int z = (int)(rest / ny2) - 1;
-        u[i] = s[state_offset(g, x, y, z)];
+                                                R *__restrict__ u, int64_t rows) {
+    const int nx2 = g.n[0] + 2, ny2 = g.n[1] + 2;
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const RowYZ yz = row_yz(g, (int)(r % ny2) - 1, (int)(r / ny2) - 1);
+        R *urow = u + r * nx2 + 1;
+        for (int bx = 0; bx < g.nb[0]; ++bx) {
+            const int ext = extent(g.n[0], g.e[0], bx);
+            const int lo = bx == 0 ? -1 : 0, hi = bx == g.nb[0] - 1 ? ext + 1 : ext;
+            const int x0 = bx * g.e[0];
+            const int64_t boff = yz.base + (int64_t)bx * g.bstride;
+            for (int lx = lo + (int)threadIdx.x; lx < hi; lx += blockDim.x)
+                urow[x0 + lx] = s[boff + lx];
+        }
     }
 }
 
@@ -55,15 +87,23 @@ __global__ __launch_bounds__(256) void k_gather(Geom g, const R *__restrict__ s,
 template <typename R>
 __global__ __launch_bounds__(256) void k_scale_source(Geom g, const R *__restrict__ f,
                                                       R *__restrict__ b, double h2,
-                                                      int64_t total) {
-    const int64_t nx = g.n[0], ny = g.n[1];
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(i % nx);
-        const int64_t rest = i / nx;
-        const int y = (int)(rest % ny);
-        const int z = (int)(rest / ny);
-        b[source_offset(g, x, y, z)] = (R)(h2 * (double)f[i]);
+                                                      int64_t rows) {
+    const int nx = g.n[0], ny = g.n[1];
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int y = (int)(r % ny), z = (int)(r / ny);
+        int by, ly, bz = 0, lz = 0;
+        owner(y, g.e[1], g.nb[1], by, ly);
+        if (g.ndim == 3) owner(z, g.e[2], g.nb[2], bz, lz);
+        const int64_t base = ((int64_t)bz * g.nb[1] + by) * g.nb[0] * g.sstride +
+                             ((int64_t)lz * g.e[1] + ly) * g.e[0];
+        const R *frow = f + r * nx;
+        for (int bx = 0; bx < g.nb[0]; ++bx) {
+            const int ext = extent(g.n[0], g.e[0], bx);
+            const int x0 = bx * g.e[0];
+            const int64_t boff = base + (int64_t)bx * g.sstride;
+            for (int lx = (int)threadIdx.x; lx < ext; lx += blockDim.x)
+                b[boff + lx] = (R)(h2 * (double)frow[x0 + lx]);
+        }
     }
 }
 
@@ -152,6 +192,12 @@ __global__ __launch_bounds__(256) void k_halo_send(Geom g, R *__restrict__ s, in
     }
 }
 
+// Grid of the row maps: one workgroup per row, rows strided beyond 2^20.
+static inline dim3 row_grid(int64_t rows) {
+    const int64_t gx = rows < 1 ? 1 : rows > (1 << 20) ? (1 << 20) : rows;
+    return dim3((unsigned)gx);
+}
+
 static inline int grid_for(int64_t total) {
     int64_t b = (total + 255) / 256;
     if (b > 65536) b = 65536;
@@ -162,9 +208,9 @@ static inline int grid_for(int64_t total) {
 template <typename R>
 hipError_t launch_scatter(const Geom &g, const void *u, void *s0, void *s1, bool zero_ring,
                           hipStream_t st) {
-    const int64_t total = (int64_t)(g.n[0] + 2) * (g.n[1] + 2) * (g.ndim == 3 ? g.n[2] + 2 : 1);
-    hipLaunchKernelGGL(k_scatter<R>, dim3(grid_for(total)), dim3(256), 0, st, g,
-                       (const R *)u, (R *)s0, (R *)s1, total, zero_ring ? 1 : 0);
+    const int64_t rows = (int64_t)(g.n[1] + 2) * (g.ndim == 3 ? g.n[2] + 2 : 1);
+    hipLaunchKernelGGL(k_scatter<R>, row_grid(rows), dim3(256), 0, st, g,
+                       (const R *)u, (R *)s0, (R *)s1, rows, zero_ring ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -267,17 +313,17 @@ hipError_t launch_adjoint_finish(const Geom &g, const double *gb, double h2, dou
 
 template <typename R>
 hipError_t launch_gather(const Geom &g, const void *s, void *u, hipStream_t st) {
-    const int64_t total = (int64_t)(g.n[0] + 2) * (g.n[1] + 2) * (g.ndim == 3 ? g.n[2] + 2 : 1);
-    hipLaunchKernelGGL(k_gather<R>, dim3(grid_for(total)), dim3(256), 0, st, g,
-                       (const R *)s, (R *)u, total);
+    const int64_t rows = (int64_t)(g.n[1] + 2) * (g.ndim == 3 ? g.n[2] + 2 : 1);
+    hipLaunchKernelGGL(k_gather<R>, row_grid(rows), dim3(256), 0, st, g,
+                       (const R *)s, (R *)u, rows);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_scale_source(const Geom &g, const void *f, void *b, double h2, hipStream_t st) {
-    const int64_t total = (int64_t)g.n[0] * g.n[1] * (g.ndim == 3 ? g.n[2] : 1);
-    hipLaunchKernelGGL(k_scale_source<R>, dim3(grid_for(total)), dim3(256), 0, st, g,
-                       (const R *)f, (R *)b, h2, total);
+    const int64_t rows = (int64_t)g.n[1] * (g.ndim == 3 ? g.n[2] : 1);
+    hipLaunchKernelGGL(k_scale_source<R>, row_grid(rows), dim3(256), 0, st, g,
+                       (const R *)f, (R *)b, h2, rows);
     return hipGetLastError();
 }
 
