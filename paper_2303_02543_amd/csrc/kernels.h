@@ -59,7 +59,7 @@ hipError_t launch_halo_send(const Geom &g, void *s, int64_t b0, int64_t b1, hipS
 // adjoint pass: b and res must be NULL, the state's ring must be zero, and
 // w * (the pass's input and its first depth-1 levels) is added, in that
 // order, to the FP64 interior array gacc (n_y x n_x).  depth must be one of
-// march2d_depths().
+// march2d_depths().  nt != 0: non-temporal output stores.
 template <typename R>
 hipError_t launch_sweep2d_march(const Geom &g, const void *uin, void *uout, const void *b,
                                 double *res, double *gacc, int depth, int rows, hipStream_t st,
@@ -74,7 +74,6 @@ int march2d_waves_per_cu(int depth, int mode);
 // Depths compiled for the 2D march kernel, ascending; returns the count.
 int march2d_depths(int dtype, const int **list);
 
-// nt != 0: non-temporal output stores.
 // Batched pass over the grids of a batch (Poisson kernels; see
 // k_march2d_batch).  nwork = prefix[ngrids]; res: one partial per work item
 // (NULL: no residual); store = false: residual only.
