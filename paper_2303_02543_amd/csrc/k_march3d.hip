@@ -384,8 +384,21 @@ __device__ __forceinline__ void m3_item(const Geom &g, const R *__restrict__ uin
         m3_body<R, T, MODE, false, RES>(g, uin, uout, bsrc, slot, L, oz0, oz1, ntb, sh);
 }
 
+// Waves per SIMD the pass kernels are compiled for.  FP32 at depths up to 4:
+// four (two workgroups per CU; their planes take at most 68 KiB of LDS), so
+// that one workgroup's waves compute while the other's wait at the per-step
+// barrier.  This caps the kernels at 128 VGPRs, which the FP32 Poisson pass
+// with the folded residual (131 otherwise, one workgroup per CU) meets
+// without spilling: 512^3 FP32 went from 0.672 to 0.627 ms per depth-4 pass.
+// In FP64 the cap spilled registers and was 1% slower, so FP64 and depth 5
+// keep two (the least an eight-wave workgroup implies).
+template <typename R, int T>
+constexpr int m3_waves_per_simd() {
+    return sizeof(R) == 4 && T <= 4 ? 4 : 2;
+}
+
 template <typename R, int T, int MODE, bool RES>
-__global__ __launch_bounds__(kM3Threads) void k_march3d(Geom g, const R *__restrict__ uin,
+__global__ __launch_bounds__(kM3Threads) __attribute__((amdgpu_waves_per_eu(m3_waves_per_simd<R, T>()))) void k_march3d(Geom g, const R *__restrict__ uin,
                                                  R *__restrict__ uout,
                                                  const R *__restrict__ bsrc,
                                                  double *__restrict__ res, int nstrips, int ngrp,
@@ -402,7 +415,7 @@ __global__ __launch_bounds__(kM3Threads) void k_march3d(Geom g, const R *__restr
 // belongs to grid gi with prefix[gi] <= w < prefix[gi+1]; every grid's input
 // is u[0] and its output u[1].
 template <typename R, int T, int MODE>
-__global__ __launch_bounds__(kM3Threads) void k_march3d_batch(const BatchGrid *__restrict__ grids,
+__global__ __launch_bounds__(kM3Threads) __attribute__((amdgpu_waves_per_eu(m3_waves_per_simd<R, T>()))) void k_march3d_batch(const BatchGrid *__restrict__ grids,
                                                        const int *__restrict__ prefix,
                                                        int ngrids, int zseg, int nitems) {
     using M = M3<R, T>;
